@@ -1,0 +1,22 @@
+"""libgoldbach: device-resident segmented double-sieve Goldbach verification
+on AMD Instinct MI355X (gfx950).
+
+The compute runs in the HIP library ``libgoldbach.so`` built from ``csrc/``;
+the ``_binding`` module only marshals arguments to its C ABI
+(``include/goldbach.h``).  There is no CPU fallback: every call raises if the
+library is missing.  Attributes are resolved lazily so that importing the
+``workloads`` submodule does not touch the binding.
+"""
+_API = ("GoldbachError", "Params", "autotune", "base_primes", "get_params", "is_prime_u64",
+        "lib", "release", "set_params", "table_count", "table_limit", "table_read",
+        "verify_batch", "verify_range", "RESULT_FIELDS")
+
+
+def __getattr__(name):
+    if name in _API:
+        from . import _binding
+        return getattr(_binding, name)
+    raise AttributeError(name)
+
+
+__all__ = list(_API)

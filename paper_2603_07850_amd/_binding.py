@@ -1,0 +1,190 @@
+"""ctypes binding of the libgoldbach C ABI (argument marshalling only).
+
+Names follow the C entry points of ``include/goldbach.h``.  PyTorch, when
+present, supplies the current HIP stream and device memory for
+``is_prime_u64``; it is never used for any step of the computation.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgoldbach.so")
+
+STATUS = {0: "GB_OK", 1: "GB_EINVAL", 2: "GB_ERANGE", 3: "GB_ENOMEM", 4: "GB_EHIP",
+          5: "GB_ETRUNC", 6: "GB_ENOTABLE", 7: "GB_EBUSY"}
+
+
+class GoldbachError(RuntimeError):
+    def __init__(self, status, msg):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__("%s: %s" % (self.name, msg))
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("A", ctypes.c_uint64), ("B", ctypes.c_uint64), ("P_max", ctypes.c_uint64),
+        ("verified", ctypes.c_uint64), ("max_p", ctypes.c_uint64), ("max_p_n", ctypes.c_uint64),
+        ("checksum", ctypes.c_uint64), ("n_unresolved", ctypes.c_uint64),
+        ("n_failed", ctypes.c_uint64),
+        ("unresolved", ctypes.POINTER(ctypes.c_uint64)), ("unresolved_cap", ctypes.c_uint64),
+    ]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("seg_log2", ctypes.c_uint32), ("wg_size", ctypes.c_uint32),
+                ("window", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+RESULT_FIELDS = ("A", "B", "P_max", "verified", "max_p", "max_p_n", "checksum",
+                 "n_unresolved", "n_failed")
+
+_lib = None
+
+
+def lib():
+    """Load libgoldbach.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libgoldbach.so is not built (run python -m paper_2603_07850_amd.build);"
+                          " there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    u64, vp, st = ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int
+    sig = {
+        "gb_base_primes": (st, [u64]),
+        "gb_table_limit": (u64, []),
+        "gb_table_count": (u64, []),
+        "gb_table_read": (st, [vp, u64, u64]),
+        "gb_verify_range": (st, [u64, u64, u64, vp, ctypes.POINTER(Result)]),
+        "gb_verify_batch": (st, [vp, u64, u64, vp, vp]),
+        "gb_set_params": (st, [ctypes.POINTER(Params)]),
+        "gb_get_params": (st, [ctypes.POINTER(Params)]),
+        "gb_autotune": (st, [u64, u64, u64, vp, ctypes.POINTER(Params)]),
+        "gb_is_prime_u64": (st, [vp, u64, vp, vp]),
+        "gb_release": (st, []),
+        "gb_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status, ok=(0,)):
+    if status not in ok:
+        raise GoldbachError(status, lib().gb_last_error().decode(errors="replace"))
+    return status
+
+
+def _stream(stream):
+    """hipStream_t handle: an int/None, or a torch stream (default: torch's current one)."""
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except ImportError:
+            pass
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def base_primes(limit):
+    _check(lib().gb_base_primes(int(limit)))
+
+
+def table_limit():
+    return int(lib().gb_table_limit())
+
+
+def table_count():
+    return int(lib().gb_table_count())
+
+
+def table_read(first=0, count=None):
+    import numpy as np
+    n = table_count()
+    if count is None:
+        count = n - first
+    out = np.empty(max(count, 1), dtype=np.uint32)
+    _check(lib().gb_table_read(out.ctypes.data, int(first), int(count)))
+    return out[:count]
+
+
+def _to_dict(r, unres_buf):
+    d = {f: int(getattr(r, f)) for f in RESULT_FIELDS}
+    take = min(d["n_unresolved"], int(r.unresolved_cap))
+    d["unresolved"] = [int(unres_buf[i]) for i in range(take)] if take else []
+    return d
+
+
+def verify_range(A, B, P_max, stream=None, unresolved_cap=1 << 16, allow_trunc=True):
+    """Verify every even n in [A, B]; returns a dict of the gb_result fields."""
+    buf = (ctypes.c_uint64 * max(int(unresolved_cap), 1))()
+    r = Result()
+    r.unresolved = ctypes.cast(buf, ctypes.POINTER(ctypes.c_uint64))
+    r.unresolved_cap = int(unresolved_cap)
+    st = lib().gb_verify_range(int(A), int(B), int(P_max), _stream(stream), ctypes.byref(r))
+    _check(st, ok=(0, 5) if allow_trunc else (0,))
+    d = _to_dict(r, buf)
+    d["status"] = STATUS[st]
+    return d
+
+
+def verify_batch(intervals, P_max, stream=None, unresolved_cap=1024, allow_trunc=True):
+    """Verify k intervals [(A, B), ...] in one persistent launch; list of dicts."""
+    k = len(intervals)
+    AB = (ctypes.c_uint64 * (2 * max(k, 1)))()
+    for i, (a, b) in enumerate(intervals):
+        AB[2 * i] = int(a)
+        AB[2 * i + 1] = int(b)
+    outs = (Result * max(k, 1))()
+    bufs = []
+    for i in range(k):
+        b = (ctypes.c_uint64 * max(int(unresolved_cap), 1))()
+        bufs.append(b)
+        outs[i].unresolved = ctypes.cast(b, ctypes.POINTER(ctypes.c_uint64))
+        outs[i].unresolved_cap = int(unresolved_cap)
+    st = lib().gb_verify_batch(AB, k, int(P_max), _stream(stream), outs)
+    _check(st, ok=(0, 5) if allow_trunc else (0,))
+    return [_to_dict(outs[i], bufs[i]) for i in range(k)]
+
+
+def set_params(seg_log2=18, wg_size=256, window=4096, wg_per_cu=0):
+    p = Params(int(seg_log2), int(wg_size), int(window), int(wg_per_cu))
+    _check(lib().gb_set_params(ctypes.byref(p)))
+
+
+def get_params():
+    p = Params()
+    _check(lib().gb_get_params(ctypes.byref(p)))
+    return p.as_dict()
+
+
+def autotune(A, B, P_max, stream=None):
+    p = Params()
+    _check(lib().gb_autotune(int(A), int(B), int(P_max), _stream(stream), ctypes.byref(p)))
+    return p.as_dict()
+
+
+def is_prime_u64(q):
+    """Device Miller-Rabin on a torch uint64/int64 CUDA tensor; returns a uint8 tensor."""
+    import torch
+    q = q.contiguous()
+    out = torch.empty(q.numel(), dtype=torch.uint8, device=q.device)
+    _check(lib().gb_is_prime_u64(q.data_ptr(), q.numel(), out.data_ptr(),
+                                 torch.cuda.current_stream(q.device).cuda_stream))
+    return out
+
+
+def release():
+    _check(lib().gb_release())

@@ -1,0 +1,366 @@
+// gb_sieve.hip -- the hot path: one persistent kernel whose workgroups claim
+// segments of evens from a device queue (an atomic counter in HBM, the
+// device-side counterpart of the paper's fetch_add work pool, Sec. 3.2 and
+// Alg. 1), sieve the segment's odd window into an LDS bitset (Sec. 3.1) and
+// probe every even n of the segment against the ascending candidate primes
+// (Phase 1, Sec. 3.3).
+//
+// Geometry of one segment (W = 2^LOG2W bits of LDS, halo H bits, E = W - H):
+//   evens    n = n0 + 2i, 0 <= i < cnt <= E
+//   bit b    odd q = q_lo + 2b,  q_lo = n0 - 1 - 2H   (q_lo may be negative
+//            for the first segments; every q <= 1 is marked composite)
+//   then     bit(n0 + 2i - p) = i + H - (p - 1)/2, so every candidate
+//            p <= 2H + 1 reads inside the window.
+//
+// Sieve (every q is odd):
+//   * primes 3..31   periodic 32-bit word masks, one word write per 32 odds;
+//   * primes >= 37   strided clears from max(p^2, first multiple in the
+//                    window) with LDS atomic AND; primes up to W/NT are
+//                    cleared cooperatively by the whole workgroup (each thread
+//                    keeps one bit position, so its mask is loop-invariant),
+//                    larger ones one prime per thread.
+// Probe (bit-parallel): a thread owns 32 consecutive evens.  For candidate p
+// the 32 bits q = n - p of those evens are 32 consecutive window bits, so one
+// funnel shift of two LDS words tests p against all 32 evens at once; hits are
+// removed from the thread's unresolved mask and the wave stops when no lane
+// has an unresolved even left.  Ascending p makes the first hit the minimal
+// one.  Evens still open after the window are appended to the spill list for
+// the Phase-2 kernel.
+#include "gb_arith.h"
+#include "gb_internal.h"
+
+namespace {
+
+constexpr uint32_t kPre[10] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
+constexpr uint32_t kFirstStrided = 11;  // primes[11] == 37
+
+__host__ __device__ constexpr uint32_t word_pattern(uint32_t p)
+{
+    uint32_t m = 0;
+    for (uint32_t b = 0; b < 32; b += p)
+        m |= 1u << b;
+    return m;
+}
+
+// Smallest bit index j of the window whose odd number q_lo + 2j is a multiple
+// of p and at least p^2 (saturated to 2^32 - 1).  The window start is q_lo
+// when !neg and -qneg when neg.
+__device__ __forceinline__ uint32_t first_bit(uint64_t qlo, uint64_t qneg, bool neg, uint32_t p)
+{
+    uint32_t x;  // -q_lo mod p
+    if (neg) {
+        x = gb_mod_u64_u32(qneg, p);
+    } else {
+        const uint32_t r = gb_mod_u64_u32(qlo, p);
+        x = r ? p - r : 0;
+    }
+    // 2*beta == x (mod p)
+    const uint32_t beta = (x & 1) ? (x >> 1) + (p >> 1) + 1 : (x >> 1);
+    const uint64_t p2 = (uint64_t)p * p;
+    uint64_t jsq = 0;
+    if (neg)
+        jsq = (p2 + qneg) >> 1;
+    else if (p2 > qlo)
+        jsq = (p2 - qlo) >> 1;
+    const uint64_t j = jsq > beta ? jsq : (uint64_t)beta;
+    return j > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)j;
+}
+
+// Number of table entries <= x (upper bound), x < 2^32.
+__device__ __forceinline__ uint32_t count_le(const uint32_t *primes, uint64_t nprimes, uint32_t x)
+{
+    uint64_t lo = 0, hi = nprimes;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (primes[mid] <= x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (uint32_t)lo;
+}
+
+__device__ __forceinline__ bool small_prime_35(int64_t q)
+{
+    return q == 3 || q == 5 || q == 7 || q == 11 || q == 13 || q == 17 || q == 19 || q == 23 ||
+           q == 29 || q == 31;
+}
+
+template <int LOG2W, int NT>
+__global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
+{
+    constexpr uint32_t W = 1u << LOG2W;
+    constexpr uint32_t NW = W / 32;
+    constexpr uint32_t NWAVE = NT / 64;
+    constexpr uint32_t PS = W / NT;  // cooperative-clear bound
+    __shared__ uint32_t bits[NW];
+    __shared__ unsigned long long sh_seg;
+    __shared__ unsigned long long red_sum[NWAVE];
+    __shared__ uint32_t red_cnt[NWAVE];
+    __shared__ uint32_t red_p[NWAVE];
+    __shared__ unsigned long long red_n[NWAVE];
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63;
+    const uint32_t wave = tid >> 6;
+    const uint32_t H = a.H;
+    const uint32_t H32 = H >> 5;
+    const uint64_t E = W - H;
+    const uint32_t *__restrict__ primes = a.primes;
+
+    for (;;) {
+        if (tid == 0)
+            sh_seg = atomicAdd(&a.ctr->claim, 1ull);
+        __syncthreads();
+        const uint64_t seg = sh_seg;
+        if (seg >= a.total_segs)
+            break;
+
+        // ---- locate the interval and the segment geometry (uniform) ----
+        uint32_t lo = 0, hi = a.k - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (a.iv[mid].seg_first <= seg)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const uint32_t ivx = lo;
+        const GbInterval I = a.iv[ivx];
+        const uint64_t js = seg - I.seg_first;
+        const uint64_t n0 = I.A + 2 * E * js;
+        const uint64_t rem = I.nE - E * js;
+        const uint32_t cnt = (uint32_t)(rem < E ? rem : E);
+        const uint32_t weff = cnt - 1 + H;          // bits [0, weff) are read by the probe
+        const bool neg = n0 <= 2ull * H;            // q_lo < 0
+        const uint64_t qlo = n0 - 1 - 2ull * H;     // valid when !neg
+        const uint64_t qneg = 2ull * H + 1 - n0;    // valid when neg
+        const uint64_t qhi = n0 + 2ull * cnt - 5;   // largest q any n of the segment needs
+        const uint32_t nsieve = count_le(primes, a.nprimes, gb_isqrt64(qhi));
+        const uint32_t ncoop = count_le(primes, a.nprimes, PS);
+
+        // ---- presieve: periodic masks of 3..31 ----
+        {
+            uint32_t ph[10];
+            uint32_t dec[10];
+#pragma unroll
+            for (int i = 0; i < 10; ++i) {
+                const uint32_t p = kPre[i];
+                const uint32_t x = neg ? (uint32_t)(qneg % p) : (uint32_t)((p - qlo % p) % p);
+                const uint32_t beta = (x & 1) ? (x + p) >> 1 : x >> 1;
+                ph[i] = (beta + p - (32u * tid) % p) % p;   // (beta - 32w) mod p at w = tid
+                dec[i] = (32u * NT) % p;
+            }
+            for (uint32_t w = tid; w < NW; w += NT) {
+                uint32_t m = 0;
+#pragma unroll
+                for (int i = 0; i < 10; ++i) {
+                    m |= word_pattern(kPre[i]) << ph[i];
+                    ph[i] = ph[i] >= dec[i] ? ph[i] - dec[i] : ph[i] + kPre[i] - dec[i];
+                }
+                bits[w] = ~m;
+            }
+        }
+        // restore the primes 3..31 and clear q <= 1 where the window reaches them
+        if (neg || qlo <= 35) {
+            __syncthreads();
+            const uint64_t bmax = neg ? (35 + qneg) >> 1 : (35 - qlo) >> 1;
+            for (uint64_t w = tid; w <= (bmax >> 5); w += NT) {
+                uint32_t v = bits[w];
+                for (uint32_t k = 0; k < 32; ++k) {
+                    const uint64_t b = 32 * w + k;
+                    if (b > bmax)
+                        break;
+                    const int64_t q = neg ? (int64_t)(2 * b) - (int64_t)qneg : (int64_t)(qlo + 2 * b);
+                    v = small_prime_35(q) ? (v | (1u << k)) : (v & ~(1u << k));
+                }
+                bits[w] = v;
+            }
+        }
+        __syncthreads();
+
+        // ---- strided clears, cooperative tier: 37 <= p <= W/NT ----
+        const uint32_t wend = (weff + 31) >> 5;
+        const uint32_t coop_end = ncoop < nsieve ? ncoop : nsieve;
+        for (uint32_t i = kFirstStrided; i < coop_end; ++i) {
+            const uint32_t p = primes[i];
+            const uint64_t jt = (uint64_t)first_bit(qlo, qneg, neg, p) + (uint64_t)tid * p;
+            if (jt < weff) {
+                const uint32_t mask = ~(1u << (jt & 31));
+                const uint32_t step = (NT / 32) * p;
+                for (uint32_t w = (uint32_t)(jt >> 5); w < wend; w += step)
+                    atomicAnd(&bits[w], mask);
+            }
+        }
+        // ---- strided clears, one prime per thread: W/NT < p <= isqrt(q_hi) ----
+        {
+            const uint32_t first = coop_end > kFirstStrided ? coop_end : kFirstStrided;
+            for (uint32_t i = first + tid; i < nsieve; i += NT) {
+                const uint32_t p = primes[i];
+                const uint32_t j = first_bit(qlo, qneg, neg, p);
+                if (p < weff) {
+                    for (uint32_t jj = j; jj < weff; jj += p)
+                        atomicAnd(&bits[jj >> 5], ~(1u << (jj & 31)));
+                } else if (j < weff) {
+                    atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- probe ----
+        const uint32_t nblk = (cnt + 31) >> 5;
+        uint64_t sum = 0;
+        uint32_t nres = 0;
+        uint32_t bestp = 0;
+        uint64_t bestn = 0;
+        if (n0 == 4 && tid == 0) {  // 4 = 2 + 2, the only n whose p_min is even
+            sum = 2;
+            nres = 1;
+            bestp = 2;
+            bestn = 4;
+        }
+        for (uint32_t jb = 0; jb < nblk; jb += NT) {
+            const uint32_t j = jb + tid;
+            const bool act = j < nblk;
+            uint32_t u = 0;
+            if (act) {
+                u = 0xFFFFFFFFu;
+                if (j == nblk - 1 && (cnt & 31))
+                    u = (1u << (cnt & 31)) - 1;
+                if (n0 == 4 && j == 0)
+                    u &= ~1u;
+            }
+            const uint32_t u0 = u;
+            const uint32_t wb = (act ? j : 0) + H32;
+            uint32_t lastp = 0, lasth = 0;
+            for (uint32_t k = 1; k <= a.ncand; ++k) {
+                if (__ballot(u != 0) == 0)
+                    break;
+                const uint32_t p = primes[k];
+                const uint32_t h = p >> 1;
+                const uint32_t w = wb - ((h + 31) >> 5);
+                const uint32_t x = __builtin_amdgcn_alignbit(bits[w + 1], bits[w], (0u - h) & 31);
+                const uint32_t hit = x & u;
+                if (hit) {
+                    u ^= hit;
+                    sum += (uint64_t)p * (uint32_t)__popc(hit);
+                    lastp = p;
+                    lasth = hit;
+                }
+            }
+            nres += (uint32_t)(__popc(u0) - __popc(u));
+            if (lastp > bestp) {
+                bestp = lastp;
+                bestn = n0 + 64ull * j + 2ull * (uint32_t)(__ffs(lasth) - 1);
+            }
+            while (u) {
+                const uint32_t b = __ffs(u) - 1;
+                u &= u - 1;
+                const unsigned long long idx = atomicAdd(&a.ctr->spills, 1ull);
+                if (idx < a.spill_cap) {
+                    a.spill[idx].n = n0 + 64ull * j + 2ull * b;
+                    a.spill[idx].iv = ivx;
+                    a.spill[idx].p = 0;
+                }
+            }
+        }
+
+        // ---- workgroup reduction of the segment's partial aggregates ----
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            sum += __shfl_xor(sum, off, 64);
+            nres += __shfl_xor(nres, off, 64);
+            const uint32_t op = __shfl_xor(bestp, off, 64);
+            const uint64_t on = __shfl_xor(bestn, off, 64);
+            if (op > bestp || (op == bestp && on < bestn)) {
+                bestp = op;
+                bestn = on;
+            }
+        }
+        if (lane == 0) {
+            red_sum[wave] = sum;
+            red_cnt[wave] = nres;
+            red_p[wave] = bestp;
+            red_n[wave] = bestn;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint64_t s = 0, c = 0, bn = 0;
+            uint32_t bp = 0;
+            for (uint32_t w = 0; w < NWAVE; ++w) {
+                s += red_sum[w];
+                c += red_cnt[w];
+                if (red_p[w] > bp || (red_p[w] == bp && red_n[w] < bn)) {
+                    bp = red_p[w];
+                    bn = red_n[w];
+                }
+            }
+            GbSegRecord r;
+            r.checksum = s;
+            r.verified = c;
+            r.max_p = bp;
+            r.max_n = bp ? bn : 0;
+            r.pad = 0;
+            a.rec[seg] = r;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void reset_kernel(GbCounters *ctr)
+{
+    if (threadIdx.x < sizeof(GbCounters) / 8)
+        reinterpret_cast<unsigned long long *>(ctr)[threadIdx.x] = 0;
+}
+
+template <int LOG2W, int NT>
+hipError_t launch_t(uint32_t grid, const GbProbeArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((sieve_probe_kernel<LOG2W, NT>), dim3(grid), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int LOG2W, int NT>
+hipError_t occ_t(int *n)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, sieve_probe_kernel<LOG2W, NT>, NT, 0);
+}
+
+}  // namespace
+
+int gb_probe_supported(int seg_log2, int wg_size)
+{
+    return (seg_log2 >= 18 && seg_log2 <= 20) && (wg_size == 256 || wg_size == 512 || wg_size == 1024);
+}
+
+#define GB_DISPATCH(FN, ...)                                                   \
+    switch (seg_log2 * 4096 + wg_size) {                                       \
+    case 18 * 4096 + 256: return FN<18, 256>(__VA_ARGS__);                     \
+    case 18 * 4096 + 512: return FN<18, 512>(__VA_ARGS__);                     \
+    case 18 * 4096 + 1024: return FN<18, 1024>(__VA_ARGS__);                   \
+    case 19 * 4096 + 256: return FN<19, 256>(__VA_ARGS__);                     \
+    case 19 * 4096 + 512: return FN<19, 512>(__VA_ARGS__);                     \
+    case 19 * 4096 + 1024: return FN<19, 1024>(__VA_ARGS__);                   \
+    case 20 * 4096 + 256: return FN<20, 256>(__VA_ARGS__);                     \
+    case 20 * 4096 + 512: return FN<20, 512>(__VA_ARGS__);                     \
+    case 20 * 4096 + 1024: return FN<20, 1024>(__VA_ARGS__);                   \
+    default: return hipErrorInvalidValue;                                      \
+    }
+
+hipError_t gb_launch_probe(int seg_log2, int wg_size, uint32_t grid, const GbProbeArgs &a,
+                           hipStream_t s)
+{
+    GB_DISPATCH(launch_t, grid, a, s)
+}
+
+hipError_t gb_probe_occupancy(int seg_log2, int wg_size, int *blocks_per_cu)
+{
+    GB_DISPATCH(occ_t, blocks_per_cu)
+}
+
+hipError_t gb_launch_reset(GbCounters *ctr, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, ctr);
+    return hipGetLastError();
+}

@@ -1,0 +1,87 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every entry point the
+header declares, and its host-side validation answers without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "goldbach.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gb_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def gb():
+    import paper_2603_07850_amd as g
+    return g
+
+
+def test_header_declares_the_north_star_calls():
+    names = _declared()
+    for n in ("gb_base_primes", "gb_verify_range", "gb_verify_batch", "gb_last_error",
+              "gb_is_prime_u64", "gb_autotune", "gb_release"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(gb):
+    L = gb.lib()
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_header(gb):
+    from paper_2603_07850_amd import _binding as b
+    assert ctypes.sizeof(b.Result) == 11 * 8
+    assert ctypes.sizeof(b.Params) == 16
+
+
+def test_no_table_is_reported_not_crashed(gb):
+    gb.release()
+    with pytest.raises(gb.GoldbachError) as e:
+        gb.verify_range(4, 100, 100)
+    assert e.value.name == "GB_ENOTABLE"
+    assert "gb_base_primes" in gb.lib().gb_last_error().decode()
+    with pytest.raises(gb.GoldbachError) as e:
+        gb.verify_batch([(4, 100)], 100)
+    assert e.value.name == "GB_ENOTABLE"
+    assert gb.table_limit() == 0 and gb.table_count() == 0
+
+
+def test_host_validation_of_params(gb):
+    saved = gb.get_params()
+    for bad in (dict(seg_log2=17), dict(seg_log2=21), dict(wg_size=128), dict(wg_size=2048),
+                dict(window=2), dict(window=65537), dict(wg_per_cu=65)):
+        args = dict(seg_log2=18, wg_size=256, window=4096, wg_per_cu=0)
+        args.update(bad)
+        with pytest.raises(gb.GoldbachError) as e:
+            gb.set_params(**args)
+        assert e.value.name == "GB_EINVAL"
+    gb.set_params(seg_log2=20, wg_size=1024, window=0, wg_per_cu=1)
+    assert gb.get_params() == dict(seg_log2=20, wg_size=1024, window=0, wg_per_cu=1)
+    gb.set_params(**saved)
+    assert gb.get_params() == saved
+
+
+def test_base_primes_rejects_limit_above_2_32(gb):
+    with pytest.raises(gb.GoldbachError) as e:
+        gb.base_primes(1 << 32)
+    assert e.value.name == "GB_EINVAL"
+
+
+def test_product_path_has_no_oracle_or_fallback():
+    """The package never imports, loads or links the oracle."""
+    pkg = os.path.join(ROOT, "paper_2603_07850_amd")
+    pat = re.compile(r"(import\s+oracle|from\s+oracle|liboracle|gb_oracle|\boracle\.[a-z_]+\()")
+    for dirpath, _, files in os.walk(pkg):
+        if "__pycache__" in dirpath:
+            continue
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not pat.search(src), f

@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, field by
+field (integer work, so bit-exact), on seeded ranges that span several
+segments and a ragged tail, at every launch shape the library supports, and
+on the edge cases of the method (n = 4, tiny P_max, ranges at 2^64 - 2,
+empty and single-even ranges, batches mixing all of these)."""
+import os
+import random
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("A", "B", "P_max", "verified", "max_p", "max_p_n", "checksum", "n_unresolved",
+          "n_failed", "unresolved")
+U64 = (1 << 64) - 1
+
+
+@pytest.fixture(scope="module")
+def gb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_2603_07850_amd as g
+    g.lib()
+    return g
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    return oracle
+
+
+_current = {"limit": None}
+
+
+def table(gb, limit):
+    if _current["limit"] != limit:
+        print("[gpu] gb_base_primes(%d)" % limit, flush=True)
+        gb.base_primes(limit)
+        _current["limit"] = limit
+
+
+def check(gb, O, A, B, P_max, limit, cap=1 << 16, seg_evens=1 << 16):
+    table(gb, limit)
+    g = gb.verify_range(A, B, P_max, unresolved_cap=cap)
+    o = O.verify_range(A, B, P_max, limit, cap=cap, seg_evens=seg_evens)
+    for f in FIELDS:
+        assert g[f] == o[f], (f, A, B, P_max, g[f], o[f])
+    return g
+
+
+# --- prime table ---------------------------------------------------------------
+
+@pytest.mark.parametrize("limit", [3163, 100000, 1000000, 10**8])
+def test_base_primes_exact(gb, O, limit):
+    table(gb, limit)
+    T = max(limit, 65536)
+    assert gb.table_limit() == T
+    ref = O.primes(T)
+    assert gb.table_count() == len(ref)
+    assert np.array_equal(gb.table_read(), ref)
+
+
+def test_base_primes_2_32(gb, O):
+    table(gb, 2**32 - 1)
+    ref = O.primes(2**32 - 1)
+    assert gb.table_count() == len(ref) == 203280221
+    got = gb.table_read()
+    assert np.array_equal(got, ref)
+
+
+# --- Phase-2 primality test ------------------------------------------------------
+
+def test_device_miller_rabin(gb, O):
+    import torch
+    rng = random.Random(5)
+    vals = list(range(0, 5000))
+    vals += [561, 2047, 3215031751, 3825123056546413051, U64, U64 - 58, 4294967291,
+             2**61 - 1, 2**32 + 15, (2**32 + 15) * (2**31 - 1), 2**63 + 1, 2**63 - 25]
+    vals += [rng.getrandbits(64) | 1 for _ in range(4000)]
+    vals += [rng.randrange(1 << 32, 1 << 34) | 1 for _ in range(2000)]
+    vals += [U64 - 2 * i for i in range(3000)]
+    q = torch.tensor(np.array(vals, dtype=np.uint64).view(np.int64), device="cuda")
+    got = gb.is_prime_u64(q).cpu().numpy()
+    exp = np.array([O.is_prime(v) for v in vals], dtype=np.uint8)
+    assert np.array_equal(got, exp)
+
+
+# --- the verification ---------------------------------------------------------
+
+def test_small_config_full(gb, O):
+    """[4, 10^7] with base primes <= 3163 and P_max = 65521."""
+    r = check(gb, O, 4, 10**7, 65521, 3163)
+    assert r["verified"] == 4999999 and r["n_unresolved"] == 0
+
+
+def test_worked_values(gb, O):
+    table(gb, 3163)
+    r = gb.verify_range(4, 30, 65521)
+    assert (r["verified"], r["checksum"], r["max_p"], r["max_p_n"]) == (14, 53, 7, 30)
+    assert gb.verify_range(4, 4, 100)["checksum"] == 2
+    assert gb.verify_range(6, 6, 100)["checksum"] == 3
+    assert gb.verify_range(8, 8, 100)["checksum"] == 3
+
+
+LAUNCH_SHAPES = [(lg, wg, win) for lg in (18, 19, 20) for wg in (256, 512, 1024)
+                 for win in (0, 4096, 64)]
+
+
+@pytest.mark.parametrize("shape", LAUNCH_SHAPES, ids=lambda s: "w%d_t%d_win%d" % s)
+def test_launch_shapes_identical(gb, O, shape):
+    lg, wg, win = shape
+    saved = gb.get_params()
+    try:
+        gb.set_params(seg_log2=lg, wg_size=wg, window=win)
+        # several segments at every shape plus a ragged tail
+        check(gb, O, 4, 3_000_000 + 2 * 777, 65536, 10**6)
+        check(gb, O, 10**11 + 2 * 12345, 10**11 + 2_400_000 + 2 * 31, 65536, 10**6)
+    finally:
+        gb.set_params(**saved)
+
+
+@pytest.mark.parametrize("P_max", [2, 3, 7, 31, 100, 1000, 4096, 65521])
+def test_tiny_and_mid_pmax(gb, O, P_max):
+    check(gb, O, 4, 40000, P_max, 100000, cap=40000)
+
+
+def test_unresolved_truncation_keeps_counts(gb, O):
+    table(gb, 100000)
+    r = gb.verify_range(4, 20000, 3, unresolved_cap=10)
+    o = O.verify_range(4, 20000, 3, 100000, cap=20000)
+    assert r["status"] == "GB_ETRUNC"
+    assert r["n_unresolved"] == o["n_unresolved"] and r["unresolved"] == o["unresolved"][:10]
+    assert r["checksum"] == o["checksum"] and r["verified"] == o["verified"]
+
+
+@pytest.mark.parametrize("AB", [(0, 3), (0, 4), (1, 9), (5, 9), (100, 50), (4, 6), (10, 10),
+                                (11, 11), (6, 5000), (7, 5001), (2**20 - 2, 2**20 + 2)])
+def test_normalization_edges(gb, O, AB):
+    check(gb, O, AB[0], AB[1], 65536, 3163)
+
+
+def test_segment_boundaries(gb, O):
+    """Ranges ending exactly at, one before and one after segment edges."""
+    table(gb, 10**6)
+    for lg in (18, 19):
+        gb.set_params(seg_log2=lg, wg_size=256, window=4096)
+        E = (1 << lg) - 2048
+        for d in (-2, 0, 2):
+            B = 4 + 2 * (E - 1) + d
+            check(gb, O, 4, B, 65536, 10**6)
+            check(gb, O, 10**10, 10**10 + 2 * (2 * E - 1) + d, 65536, 10**6)
+    gb.set_params(seg_log2=18, wg_size=256, window=4096, wg_per_cu=0)
+
+
+def test_near_2_64(gb, O):
+    """Top of the u64 range: the overflow guards (Sec. 3.4)."""
+    T = 2**32 - 1
+    check(gb, O, U64 - 2 * 30000, U64, 65536, T, seg_evens=1 << 22)
+    check(gb, O, U64 - 1, U64, 65536, T, seg_evens=1 << 22)
+    check(gb, O, U64, U64, 65536, T)
+    check(gb, O, U64 - 2 * 5000 - 1, U64 - 3, 7, T, cap=20000, seg_evens=1 << 22)
+
+
+def test_table_too_small_is_erange(gb):
+    table(gb, 3163)
+    with pytest.raises(gb.GoldbachError) as e:
+        gb.verify_range(4, 10**12, 65536)
+    assert e.value.name == "GB_ERANGE"
+    with pytest.raises(gb.GoldbachError) as e:
+        gb.verify_range(4, 100, 70000)
+    assert e.value.name == "GB_ERANGE"
+    with pytest.raises(gb.GoldbachError) as e:
+        gb.verify_range(4, 100, 1)
+    assert e.value.name == "GB_EINVAL"
+
+
+def test_batch_equals_single_calls_and_oracle(gb, O):
+    table(gb, 2**32 - 1)
+    ivs = [(4, 100000), (100, 50), (10**9, 10**9 + 300000), (U64 - 40000, U64),
+           (10**12 + 2, 10**12 + 2), (5, 5), (10**15 + 1, 10**15 + 1 + 2 * 123457),
+           (2**40, 2**40 + 2 * 70000), (4, 100000)]
+    got = gb.verify_batch(ivs, 65536)
+    for (A, B), g in zip(ivs, got):
+        s = gb.verify_range(A, B, 65536)
+        o = O.verify_range(A, B, 65536, 2**32 - 1, seg_evens=1 << 22)
+        for f in FIELDS:
+            assert g[f] == s[f] == o[f], (f, A, B)
+
+
+def test_batch_with_tiny_pmax(gb, O):
+    table(gb, 100000)
+    ivs = [(4, 3000), (2000, 9000), (50000, 51000)]
+    got = gb.verify_batch(ivs, 5, unresolved_cap=5000)
+    for (A, B), g in zip(ivs, got):
+        o = O.verify_range(A, B, 5, 100000, cap=5000)
+        for f in FIELDS:
+            assert g[f] == o[f], (f, A, B)
+
+
+def test_repeat_runs_identical(gb):
+    table(gb, 10**6)
+    a = gb.verify_range(10**11, 10**11 + 4 * 10**6, 65536)
+    for _ in range(3):
+        assert gb.verify_range(10**11, 10**11 + 4 * 10**6, 65536) == a
