@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark of libgoldbach on one MI355X.
+
+Headline (the metric's configuration): verify every even n in [4, 10^12]
+with base primes <= 10^6 and P_max = 2^16 -- the paper's single-GPU headline
+range (Table 1).  One step = build the base-prime table + verify the whole
+range, i.e. every step of the hot path; the table build is inside the step
+because the paper's wall-clock includes initialisation.
+
+Prints ONE JSON line (rank 0) with value = even n verified per second.
+
+Extra legs (also in the JSON line):
+  roofline      the sieve+probe kernel's algorithmic lane-op rate against the
+                gfx950 VALU peak, the kernel time taken from HIP events
+                recorded by the library on the launch stream;
+  cpu_baseline  the CPU oracle, timed on this host's cores over a bounded
+                sample of seeded 10^7-wide windows of the same range;
+  batched       (--batched) 4096 seeded uneven intervals in one persistent
+                launch vs one launch per interval, with p50/p99 latency.
+
+Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
+       python bench.py --copy-calibration     (plain 1 GiB copies, for counters)
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HEADLINE = {"A": 4, "B": 10**12, "P_max": 65536, "limit": 10**6}
+# paper Table 1: [4, 10^12] in 36,511.6 ms on one RTX 5090 (another machine)
+PAPER_SECONDS_1E12 = 36.5116
+# gfx950 VALU: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one 32-bit integer op per lane per clock
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# price of one strike or one word-test in 32-bit lane-ops (the low end of the
+# 4-6 lane-ops per sieve clear or probe test of the work model)
+OPS_PER_WORD_OP = 4.0
+
+
+def evens_in(A, B):
+    a = max(4, A + (A & 1))
+    b = B - (B & 1)
+    return 0 if a > b else (b - a) // 2 + 1
+
+
+def work_model():
+    with open(os.path.join(ROOT, "tests", "golden", "work_model.json")) as f:
+        return json.load(f)
+
+
+def algorithmic_ops_per_even(wm, seg_log2, halo_bits):
+    """Strikes and word-tests per even of the headline range, priced in lane-ops.
+
+    strikes per odd (primes 37..sqrt(q), Mertens sum over the real table), one
+    presieve word write per 32 odds, all scaled by the halo factor W/(W-H)
+    (window bits per even); word-tests per even = mean max rank of a 32-even
+    block / 32 (the word-parallel probe tests a block against every candidate
+    up to its largest p_min)."""
+    h = wm["headline"]
+    W = 1 << seg_log2
+    halo = W / (W - halo_bits)
+    strikes = (h["strikes_per_odd"] + 1.0 / 32) * halo
+    tests = h["mean_block_max_rank"] / 32.0
+    return OPS_PER_WORD_OP * (strikes + tests)
+
+
+def cpu_baseline(sample_windows):
+    """The oracle, as it stands, over seeded windows of the headline range."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import oracle as O
+    from paper_2603_07850_amd import workloads as Wl
+    wins = Wl.windows(7070, sample_windows, 4, HEADLINE["B"])
+    O.primes(HEADLINE["limit"])                      # table built before the clock
+    O.primes(max(HEADLINE["limit"], 65536))
+    cores = min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:   # ctypes releases the GIL
+        res = list(ex.map(lambda w: O.verify_range(w[0], w[1], HEADLINE["P_max"],
+                                                   HEADLINE["limit"]), wins))
+    dt = time.perf_counter() - t0
+    ev = sum(r["verified"] for r in res)
+    return {"value": ev / dt, "unit": "even n verified/s", "cores": cores, "kind": "oracle",
+            "sample": "%d seeded 1e7-wide windows of [4, 1e12] (%d evens), %d threads, %.1f s wall"
+                      % (len(wins), ev, cores, dt)}
+
+
+def run_batched(gb, steps):
+    """4096 seeded uneven intervals: one persistent launch vs one launch each."""
+    import statistics
+
+    from paper_2603_07850_amd import workloads as Wl
+    ivs = Wl.batch_intervals()
+    ev = sum(evens_in(a, b) for a, b in ivs)
+    gb.base_primes(2**32 - 1)
+    gb.verify_batch(ivs[:64], 65536)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = gb.verify_batch(ivs, 65536)
+    dt = (time.perf_counter() - t0) / steps
+    lat = gb.last_batch_latencies()
+    t0 = time.perf_counter()
+    done = []
+    for a, b in ivs:
+        gb.verify_range(a, b, 65536)
+        done.append(time.perf_counter() - t0)
+    dt1 = done[-1]
+    q = lambda xs, p: sorted(xs)[min(len(xs) - 1, int(p * len(xs)))]
+    return {
+        "intervals": len(ivs), "evens": ev,
+        "batched_evens_per_s": ev / dt, "batched_s": dt,
+        "per_interval_evens_per_s": ev / dt1, "per_interval_s": dt1,
+        "p50_ms": q(lat, 0.5) * 1e3, "p99_ms": q(lat, 0.99) * 1e3,
+        "per_interval_p50_ms": q(done, 0.5) * 1e3, "per_interval_p99_ms": q(done, 0.99) * 1e3,
+        "all_verified": all(r["n_failed"] == 0 for r in res),
+        "median_batched_latency_ms": statistics.median(lat) * 1e3,
+    }
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 30
+    x = torch.empty(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty(n, dtype=torch.uint8, device="cuda")
+    x.fill_(1)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-windows", type=int, default=96)
+    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build measures one MI355X; --gpus %d is not supported "
+              "(the verification shards by segments, see the design notes)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import paper_2603_07850_amd as gb
+    A, B, P_max, limit = HEADLINE["A"], HEADLINE["B"], HEADLINE["P_max"], HEADLINE["limit"]
+    evens = evens_in(A, B)
+
+    gb.base_primes(limit)
+    if not args.no_autotune:
+        # autotuner: calibration on the top 2*10^10 of the range (results unaffected)
+        params = gb.autotune(B - 4 * 10**10, B, P_max)
+    params = gb.get_params()
+
+    def step():
+        gb.base_primes(limit)
+        return gb.verify_range(A, B, P_max)
+
+    for _ in range(args.warmup):
+        ref = step()
+    torch.cuda.synchronize()
+    probe_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = step()
+        probe_ms.append(gb.last_stats()["probe_ms"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = gb.last_stats()
+    ok = (r["verified"] == evens and r["n_unresolved"] == 0 and r["n_failed"] == 0)
+    if args.warmup:
+        ok = ok and all(r[f] == ref[f] for f in ("checksum", "max_p", "max_p_n"))
+    value = evens * args.steps / dt
+
+    wm = work_model()
+    ops_even = algorithmic_ops_per_even(wm, st["seg_log2"], st["halo_bits"])
+    kern_s = sum(probe_ms) / len(probe_ms) / 1e3
+    achieved = ops_even * evens / kern_s
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                "kernel": "sieve_probe_kernel", "kernel_ms": kern_s * 1e3,
+                "ops_per_even": ops_even}
+
+    out = {
+        "metric": "even n verified/sec at 1 GPU (to 1e12)",
+        "value": value, "unit": "even n verified/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": value / (evens / PAPER_SECONDS_1E12),
+        "dtype": "u64", "data": "synthetic (the range itself; no dataset)",
+        "config": {"workload": "all even n in [4, 1e12]", "A": A, "B": B, "P_max": P_max,
+                   "base_prime_limit": limit, "params": params, "parallelism": "single GPU"},
+        "result": {k: r[k] for k in ("verified", "checksum", "max_p", "max_p_n",
+                                     "n_unresolved", "n_failed")},
+        "results_consistent": ok,
+        "roofline": roofline,
+    }
+    if args.batched:
+        out["batched"] = run_batched(gb, 2)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_windows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

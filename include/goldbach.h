@@ -83,8 +83,9 @@ typedef struct gb_result {
 /*
  * Launch parameters of the segment sieve + probe kernel (scheduling only:
  * they never change a result field).
- *   seg_log2   log2 of the odd numbers held per segment bitset in LDS:
- *              18, 19 or 20 (32, 64 or 128 KB of LDS per workgroup).
+ *   seg_log2   log2 of the evens per segment: 18, 19 or 20; the segment's
+ *              LDS window holds 2^seg_log2 + halo odd numbers as bits
+ *              (about 32, 64 or 128 KB per workgroup).
  *   wg_size    threads per workgroup: 256, 512 or 1024.
  *   window     probe window: candidates p <= min(P_max, window) are tested in
  *              LDS by the probe; candidates window < p <= P_max are tested by
@@ -92,12 +93,19 @@ typedef struct gb_result {
  *              0 means window = P_max.  Must be 0 or in [3, 65536].
  *   wg_per_cu  workgroups per compute unit in the persistent grid; 0 = the
  *              maximum that LDS allows.
+ *   bucket_log2  primes above 2^bucket_log2 are not sieved segment by segment
+ *              but through per-segment bucket lists filled once per run of
+ *              segments; 0 = seg_log2 + 1, else 17..32 (32 = never).
+ *   bucket_mib HBM budget for the bucket lists of one round, in MiB
+ *              (0 = 4096); larger batches run in several rounds.
  */
 typedef struct gb_params {
     uint32_t seg_log2;
     uint32_t wg_size;
     uint32_t window;
     uint32_t wg_per_cu;
+    uint32_t bucket_log2;
+    uint32_t bucket_mib;
 } gb_params;
 
 /*
@@ -137,8 +145,10 @@ gb_status gb_verify_range(uint64_t A, uint64_t B, uint64_t P_max, void *stream,
 
 /*
  * Verify k ranges in one persistent launch (batched form): workgroups claim
- * segments of all k ranges from one device queue with an atomic counter.
- * Results are identical to k separate gb_verify_range() calls.
+ * segments of all k ranges from one device queue with an atomic counter, and
+ * the whole launch sequence is a captured HIP graph, re-instantiated only when
+ * the batch's shape changes.  Results are identical to k separate
+ * gb_verify_range() calls.
  *   AB     host array of 2k u64: A_0, B_0, A_1, B_1, ...
  *   outs   host array of k gb_result (unresolved buffers as in gb_verify_range).
  * Errors as gb_verify_range; GB_ETRUNC if any list was truncated.
@@ -152,7 +162,7 @@ gb_status gb_set_params(const gb_params *p);
 gb_status gb_get_params(gb_params *p);
 
 /*
- * Time a calibration run of [A, B] (at most 2^31 evens) under each supported
+ * Time a calibration run of [A, B] (at most 2^36 evens) under each supported
  * parameter set, keep the fastest as the current parameters and write it to
  * *best (may be NULL).  Results of later calls do not depend on the choice.
  */
@@ -168,6 +178,101 @@ gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream,
  */
 gb_status gb_is_prime_u64(const uint64_t *q, uint64_t count, uint8_t *is_prime,
                           void *stream);
+
+/*
+ * Measurements of the last gb_verify_range / gb_verify_batch call, for the
+ * benchmark and the profiles.
+ *   probe_ms     duration of the persistent sieve+probe kernel, from HIP events
+ *                recorded on the caller's stream around that launch.
+ *   total_ms     the whole launch sequence on the stream (events around it).
+ *   segments     segments processed; evens = evens in all ranges.
+ *   spills       evens left open by the probe window (handled by Phase 2).
+ *   grid, wg_size, seg_log2, halo_bits, ncand   the launch shape used.
+ *   intervals    number of intervals of the call.
+ */
+typedef struct gb_stats {
+    double probe_ms;
+    double total_ms;
+    uint64_t segments;
+    uint64_t evens;
+    uint64_t spills;
+    uint32_t grid;
+    uint32_t wg_size;
+    uint32_t seg_log2;
+    uint32_t halo_bits;
+    uint32_t ncand;
+    uint32_t pad;
+    uint64_t intervals;
+} gb_stats;
+
+gb_status gb_last_stats(gb_stats *out);
+
+/*
+ * Per-interval latency of the last verify call, in milliseconds: from the
+ * start of its launch sequence on the device to the moment the interval's
+ * last segment finished (device wall clock; 0 for an empty interval).
+ * k must equal the number of intervals of that call; ms is caller-owned.
+ */
+gb_status gb_last_latencies(double *ms, uint64_t k);
+
+/*
+ * Served form: a request loop with continuous batching.  A server thread
+ * admits submitted ranges while active slots and the HBM budget allow, and
+ * runs ticks in which every active request contributes its next piece
+ * (piece_segments segments) to one batched launch (gb_verify_batch); requests
+ * arriving during a tick join the next one.  Pieces of a request are taken in
+ * ascending n and merged, so every result equals gb_verify_range of the same
+ * range.  The prime table must exist (gb_base_primes) and must not be
+ * rebuilt or released while a server is open.
+ *
+ *   hbm_budget_bytes  admission budget: the sum of the active requests'
+ *                     reservations (bucket lists and records of one piece,
+ *                     estimated from the range's top) stays within it; a
+ *                     request whose reservation alone exceeds it is refused
+ *                     with GB_ENOMEM at submission.
+ *   P_max             candidate bound for every request (as gb_verify_range).
+ *   max_active        slots: requests verified concurrently.
+ *   piece_segments    segments per request per tick (>= 1).
+ *   max_pending       bound on queued, not yet admitted requests (0 = none);
+ *                     GB_EBUSY at submission when full.
+ */
+typedef struct gb_server gb_server;
+
+typedef struct gb_server_config {
+    uint64_t hbm_budget_bytes;
+    uint64_t P_max;
+    uint32_t max_active;
+    uint32_t piece_segments;
+    uint32_t max_pending;
+    uint32_t pad;
+} gb_server_config;
+
+/* Counters of a server since it was opened (wall_ms: time since open; busy_ms:
+ * time spent inside batched launches). */
+typedef struct gb_server_stats {
+    uint64_t submitted, admitted, completed, completed_evens, ticks;
+    uint64_t active, pending, reserved_bytes;
+    double busy_ms, wall_ms;
+} gb_server_stats;
+
+/* Open a server on the current table and parameters; *out owns a host thread. */
+gb_status gb_server_open(const gb_server_config *cfg, gb_server **out);
+
+/* Queue [A, B] (any u64 pair, normalized as for gb_result); *id (may be NULL)
+ * receives the request id.  Non-blocking. */
+gb_status gb_server_submit(gb_server *s, uint64_t A, uint64_t B, uint64_t *id);
+
+/* Take one finished request: waits up to wait_ms (0 = do not wait, < 0 = until
+ * one finishes); GB_EBUSY if none.  *out as for gb_verify_range (its
+ * unresolved buffer is filled, GB_ETRUNC if too small); *latency_ms is the
+ * time from submission to completion. */
+gb_status gb_server_poll(gb_server *s, int32_t wait_ms, uint64_t *id, gb_result *out,
+                         double *latency_ms);
+
+gb_status gb_server_get_stats(gb_server *s, gb_server_stats *out);
+
+/* Finish the active requests, drop the queued ones, stop the thread, free s. */
+gb_status gb_server_close(gb_server *s);
 
 /* Free the prime table and every workspace.  Safe to call at any time. */
 gb_status gb_release(void);

@@ -33,10 +33,33 @@ class Result(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("seg_log2", ctypes.c_uint32), ("wg_size", ctypes.c_uint32),
-                ("window", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32)]
+                ("window", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32),
+                ("bucket_log2", ctypes.c_uint32), ("bucket_mib", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("probe_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("segments", ctypes.c_uint64), ("evens", ctypes.c_uint64),
+                ("spills", ctypes.c_uint64), ("grid", ctypes.c_uint32),
+                ("wg_size", ctypes.c_uint32), ("seg_log2", ctypes.c_uint32),
+                ("halo_bits", ctypes.c_uint32), ("ncand", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("intervals", ctypes.c_uint64)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("P_max", ctypes.c_uint64),
+                ("max_active", ctypes.c_uint32), ("piece_segments", ctypes.c_uint32),
+                ("max_pending", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("submitted", "admitted", "completed",
+                                               "completed_evens", "ticks", "active",
+                                               "pending", "reserved_bytes")] + \
+               [("busy_ms", ctypes.c_double), ("wall_ms", ctypes.c_double)]
 
 
 RESULT_FIELDS = ("A", "B", "P_max", "verified", "max_p", "max_p_n", "checksum",
@@ -66,6 +89,14 @@ def lib():
         "gb_get_params": (st, [ctypes.POINTER(Params)]),
         "gb_autotune": (st, [u64, u64, u64, vp, ctypes.POINTER(Params)]),
         "gb_is_prime_u64": (st, [vp, u64, vp, vp]),
+        "gb_last_stats": (st, [ctypes.POINTER(Stats)]),
+        "gb_last_latencies": (st, [vp, u64]),
+        "gb_server_open": (st, [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
+        "gb_server_submit": (st, [vp, u64, u64, ctypes.POINTER(u64)]),
+        "gb_server_poll": (st, [vp, ctypes.c_int32, ctypes.POINTER(u64), ctypes.POINTER(Result),
+                                ctypes.POINTER(ctypes.c_double)]),
+        "gb_server_get_stats": (st, [vp, ctypes.POINTER(ServerStats)]),
+        "gb_server_close": (st, [vp]),
         "gb_release": (st, []),
         "gb_last_error": (ctypes.c_char_p, []),
     }
@@ -159,8 +190,9 @@ def verify_batch(intervals, P_max, stream=None, unresolved_cap=1024, allow_trunc
     return [_to_dict(outs[i], bufs[i]) for i in range(k)]
 
 
-def set_params(seg_log2=18, wg_size=256, window=4096, wg_per_cu=0):
-    p = Params(int(seg_log2), int(wg_size), int(window), int(wg_per_cu))
+def set_params(seg_log2=18, wg_size=256, window=4096, wg_per_cu=0, bucket_log2=0, bucket_mib=0):
+    p = Params(int(seg_log2), int(wg_size), int(window), int(wg_per_cu), int(bucket_log2),
+               int(bucket_mib))
     _check(lib().gb_set_params(ctypes.byref(p)))
 
 
@@ -186,5 +218,69 @@ def is_prime_u64(q):
     return out
 
 
+def last_stats():
+    s = Stats()
+    _check(lib().gb_last_stats(ctypes.byref(s)))
+    return {f: (float(getattr(s, f)) if f.endswith("_ms") else int(getattr(s, f)))
+            for f, _ in Stats._fields_ if f != "pad"}
+
+
+def last_batch_latencies():
+    """Per-interval device latency (seconds) of the last verify call."""
+    k = last_stats()["intervals"]
+    buf = (ctypes.c_double * max(k, 1))()
+    _check(lib().gb_last_latencies(buf, k))
+    return [buf[i] / 1e3 for i in range(k)]
+
+
 def release():
     _check(lib().gb_release())
+
+
+class Server:
+    """Served form: continuous batching of submitted ranges (gb_server_*)."""
+
+    def __init__(self, P_max, hbm_budget_bytes=64 << 30, max_active=64, piece_segments=256,
+                 max_pending=0):
+        cfg = ServerConfig(int(hbm_budget_bytes), int(P_max), int(max_active),
+                           int(piece_segments), int(max_pending), 0)
+        self._h = ctypes.c_void_p()
+        _check(lib().gb_server_open(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self.P_max = int(P_max)
+
+    def submit(self, A, B):
+        rid = ctypes.c_uint64()
+        _check(lib().gb_server_submit(self._h, int(A), int(B), ctypes.byref(rid)))
+        return int(rid.value)
+
+    def poll(self, wait_ms=-1, unresolved_cap=1024):
+        """(id, result dict, latency seconds), or None if nothing finished in time."""
+        buf = (ctypes.c_uint64 * max(int(unresolved_cap), 1))()
+        r = Result()
+        r.unresolved = ctypes.cast(buf, ctypes.POINTER(ctypes.c_uint64))
+        r.unresolved_cap = int(unresolved_cap)
+        rid = ctypes.c_uint64()
+        lat = ctypes.c_double()
+        st = lib().gb_server_poll(self._h, int(wait_ms), ctypes.byref(rid), ctypes.byref(r),
+                                  ctypes.byref(lat))
+        if st == 7:
+            return None
+        _check(st, ok=(0, 5))
+        return int(rid.value), _to_dict(r, buf), lat.value / 1e3
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib().gb_server_get_stats(self._h, ctypes.byref(s)))
+        return {f: (float(getattr(s, f)) if f.endswith("_ms") else int(getattr(s, f)))
+                for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            _check(lib().gb_server_close(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,151 @@
+// gb_bucket.hip -- bucket lists for the primes above the bucket bound.
+//
+// A prime p much larger than a segment window strikes a window at most once,
+// so computing its first multiple in every segment (one 64-by-32-bit
+// remainder per prime per segment) costs far more than the strikes
+// themselves; near 2^64 there are 2*10^8 such primes per segment.  Here the
+// remainder is taken once per chunk (a run of consecutive segments of one
+// interval) and prime, the prime's multiples are walked across the chunk, and
+// each strike is appended, as a window bit offset, to the bucket of the
+// segment that owns it -- and of the previous segment too when it falls in
+// the halo the two windows share.  The segment kernel then clears its
+// bucket's bits in LDS.
+//
+// Work is cut into items (prime, sub-range of the chunk): primes of the band
+// (2^b, 2^(b+1)] get sub-ranges of 8 * 2^b bits, so an item takes one
+// remainder and makes at most 16 strikes whatever the prime's size.  Every
+// offset is relative to the chunk's window start and bounded by the chunk's
+// last odd number, so no absolute value beyond it is formed (the overflow
+// guards of the paper's Sec. 3.4).
+#include "gb_arith.h"
+#include "gb_internal.h"
+
+namespace {
+
+__device__ __forceinline__ void append(const GbBucketArgs &a, uint64_t g, uint32_t off)
+{
+    const uint64_t rel = g - a.seg_base;
+    const uint32_t idx = atomicAdd(&a.bcount[rel], 1u);
+    if (idx < a.bcap)
+        a.bucket[rel * a.bcap + idx] = off;
+}
+
+__global__ __launch_bounds__(kFillThreads) void bucket_fill_kernel(GbBucketArgs a)
+{
+    const uint64_t tile = blockIdx.x;
+    if (tile >= a.ntiles)
+        return;
+    uint32_t lo = 0, hi = a.ntask - 1;   // last task whose first tile <= tile
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (a.task[mid].tile_first <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const GbFillTask T = a.task[lo];
+    const GbChunk C = a.chunk[T.chunk];
+    const uint32_t E = 1u << a.log2e;
+    const uint32_t emask = E - 1;
+    const uint64_t items = (uint64_t)T.np * T.nsub;
+    const uint64_t base = (tile - T.tile_first) * (uint64_t)(kFillThreads * kFillPerThread);
+    for (uint32_t m = 0; m < kFillPerThread; ++m) {
+        const uint64_t w = base + threadIdx.x + (uint64_t)m * kFillThreads;
+        if (w >= items)
+            break;
+        const uint32_t pi = (uint32_t)(w % T.np);
+        const uint32_t j = (uint32_t)(w / T.np);
+        const uint64_t idx = (uint64_t)T.p_first + pi;
+        if (idx >= C.p_root)
+            continue;
+        const uint32_t p = a.primes[idx];
+        const uint64_t b0 = (uint64_t)j << T.sl_log2;        // first bit of the sub-range
+        if (b0 > C.dmax)
+            continue;
+        uint64_t b1 = b0 + (1ull << T.sl_log2) - 1;          // last bit of the sub-range
+        if (b1 > C.dmax)
+            b1 = C.dmax;
+        // first odd multiple of p at or above max(Q0 + 2*b0, p^2), as a window bit
+        const uint64_t qs = C.Q0 + 2 * b0;                   // <= the chunk's last odd number
+        const uint32_t r = gb_mod_u64_u32(qs, p);
+        uint64_t x = r ? p - r : 0;
+        if (x & 1)
+            x += p;                                          // qs is odd: x must be even
+        uint64_t d = b0 + (x >> 1);
+        const uint64_t p2 = (uint64_t)p * p;
+        if (p2 > C.Q0) {
+            const uint64_t dsq = (p2 - C.Q0) >> 1;
+            if (dsq > d)
+                d = dsq;
+        }
+        for (; d <= b1; d += p) {
+            const uint64_t s = d >> a.log2e;
+            const uint32_t off = (uint32_t)d & emask;
+            if (s < C.nseg)
+                append(a, C.seg_first + s, off);
+            if (off < a.H && s >= 1 && s - 1 < C.nseg)
+                append(a, C.seg_first + s - 1, off + E);
+        }
+    }
+}
+
+__global__ void bucket_reset_kernel(uint32_t *bcount, uint64_t nsegs)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsegs; i += stride)
+        bcount[i] = 0;
+}
+
+// p_root of each chunk: the number of table primes <= isqrt(its top).
+__global__ void chunk_roots_kernel(const uint32_t *primes, uint64_t nprimes, GbChunk *chunks,
+                                   uint64_t nchunk)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchunk; c += stride) {
+        const uint32_t root = gb_isqrt64(chunks[c].Q0 + 2 * chunks[c].dmax);
+        uint64_t lo = 0, hi = nprimes;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (primes[mid] <= root)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        chunks[c].p_root = (uint32_t)lo;
+    }
+}
+
+}  // namespace
+
+hipError_t gb_launch_bucket_reset(uint32_t *bcount, uint64_t nsegs, unsigned long long *,
+                                  hipStream_t s)
+{
+    uint64_t blocks = (nsegs + 255) / 256;
+    if (blocks < 1)
+        blocks = 1;
+    if (blocks > 4096)
+        blocks = 4096;
+    hipLaunchKernelGGL(bucket_reset_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, bcount, nsegs);
+    return hipGetLastError();
+}
+
+hipError_t gb_launch_bucket_fill(const GbBucketArgs &a, uint32_t grid, hipStream_t s)
+{
+    if (grid == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(bucket_fill_kernel, dim3(grid), dim3(kFillThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t gb_launch_chunk_roots(const uint32_t *primes, uint64_t nprimes, GbChunk *chunks,
+                                 uint64_t nchunk, hipStream_t s)
+{
+    if (nchunk == 0)
+        return hipSuccess;
+    uint64_t blocks = (nchunk + 255) / 256;
+    if (blocks > 1024)
+        blocks = 1024;
+    hipLaunchKernelGGL(chunk_roots_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, primes, nprimes,
+                       chunks, nchunk);
+    return hipGetLastError();
+}

@@ -44,12 +44,21 @@ struct GbIvResult {
 
 // Device counters of one launch; cleared by gb_launch_reset at the start.
 struct GbCounters {
-    unsigned long long claim;   // next segment to claim
-    unsigned long long spills;  // spill entries appended (may exceed the capacity)
-    unsigned long long pad[6];
+    unsigned long long claim;    // unused (each launch has its own queue head)
+    unsigned long long spills;   // spill entries appended (may exceed the capacity)
+    unsigned long long t_start;  // device wall clock when the launch sequence began
+    unsigned long long pad[5];   // pad[0]: largest overflowing bucket count
 };
 
-// Arguments of the persistent sieve + probe kernel.
+// Per-interval completion: segments finished and the device wall clock when
+// the interval's last segment finished (the batched form's latency).
+struct GbIvDone {
+    unsigned long long segs_done;
+    unsigned long long t_done;
+};
+
+// Arguments of the persistent sieve + probe kernel.  One launch processes the
+// segments [seg_base, seg_base + nsegs) of the global segment numbering.
 struct GbProbeArgs {
     const uint32_t *primes;   // the prime table, ascending, primes[0] = 2
     uint64_t nprimes;
@@ -57,13 +66,61 @@ struct GbProbeArgs {
     uint32_t k;               // number of intervals
     uint32_t H;               // halo in bits (multiple of 32)
     uint32_t ncand;           // odd candidates probed in LDS: primes[1 .. ncand]
-    uint32_t pad;
-    uint64_t total_segs;
+    uint32_t lb_count;        // primes[0 .. lb_count) are sieved in the segment
+    uint64_t seg_base;
+    uint64_t nsegs;
     GbSegRecord *rec;
     GbSpill *spill;
     uint64_t spill_cap;
     GbCounters *ctr;
+    unsigned long long *claim;  // this launch's segment queue head
+    GbIvDone *done;
+    const uint32_t *bucket;   // per segment: bcap window bits struck by large primes
+    const uint32_t *bcount;   // per segment: entries appended (may exceed bcap)
+    uint32_t bcap;            // 0 when the launch has no buckets
+    uint32_t pad;
+    unsigned long long *bover;  // largest bucket count seen above bcap (overflow report)
 };
+
+// A run of consecutive segments of one interval that the bucket-fill kernel
+// treats as one window [Q0, Q0 + 2*dmax] of odd numbers.
+struct GbChunk {
+    uint64_t seg_first;   // global index of the chunk's first segment
+    uint64_t Q0;          // odd number at window bit 0 of the first segment
+    uint64_t dmax;        // last window bit any segment of the chunk reads
+    uint32_t nseg;
+    uint32_t p_root;      // one past the last table prime <= isqrt(Q0 + 2*dmax)
+};
+
+// One fill task: the table primes [p_first, p_first + np) of one band
+// (2^b, 2^(b+1)] against one chunk cut into nsub sub-ranges of 2^sl_log2 bits,
+// so that a work item (prime, sub-range) has one remainder and a few strikes.
+struct GbFillTask {
+    uint64_t tile_first;  // first fill tile of the task (within the round)
+    uint32_t chunk;       // index into the round's chunks
+    uint32_t p_first;
+    uint32_t np;          // an upper bound; items past the chunk's p_root exit
+    uint32_t nsub;
+    uint32_t sl_log2;
+    uint32_t pad;
+};
+
+struct GbBucketArgs {
+    const uint32_t *primes;
+    const GbChunk *chunk;
+    const GbFillTask *task;
+    uint32_t ntask;
+    uint32_t log2e;
+    uint32_t H;
+    uint32_t bcap;
+    uint64_t ntiles;
+    uint64_t seg_base;    // global index of the round's first segment
+    uint32_t *bucket;
+    uint32_t *bcount;
+};
+
+// Set the calling thread's gb_last_error() message (host code).
+void gb_internal_set_error(const char *msg);
 
 // Launch wrappers (each returns the hipError_t of its launch).
 hipError_t gb_launch_seed(uint32_t *seed, uint32_t *nseed, hipStream_t s);
@@ -75,11 +132,23 @@ hipError_t gb_launch_table_emit(const uint32_t *seed, const uint32_t *nseed, uin
                                 hipStream_t s);
 uint32_t gb_table_seg_log2();
 
-hipError_t gb_launch_reset(GbCounters *ctr, hipStream_t s);
+hipError_t gb_launch_reset(GbCounters *ctr, GbIvDone *done, uint32_t k,
+                           unsigned long long *claims, uint32_t nclaims, hipStream_t s);
+hipError_t gb_launch_pow2_counts(const uint32_t *primes, uint64_t nprimes, uint64_t *out33,
+                                 hipStream_t s);
+hipError_t gb_launch_chunk_roots(const uint32_t *primes, uint64_t nprimes, GbChunk *chunks,
+                                 uint64_t nchunk, hipStream_t s);
 hipError_t gb_launch_probe(int seg_log2, int wg_size, uint32_t grid, const GbProbeArgs &a,
                            hipStream_t s);
 int gb_probe_supported(int seg_log2, int wg_size);
 hipError_t gb_probe_occupancy(int seg_log2, int wg_size, int *blocks_per_cu);
+
+constexpr uint32_t kFillThreads = 256;
+constexpr uint32_t kFillPerThread = 4;   // work items per thread in one fill tile
+constexpr uint32_t kFillStrikes = 8;     // sub-range = kFillStrikes * 2^b bits for band b
+hipError_t gb_launch_bucket_reset(uint32_t *bcount, uint64_t nsegs, unsigned long long *bover,
+                                  hipStream_t s);
+hipError_t gb_launch_bucket_fill(const GbBucketArgs &a, uint32_t grid, hipStream_t s);
 
 hipError_t gb_launch_phase2(const uint32_t *primes, uint64_t nprimes, uint64_t first_idx,
                             GbSpill *spill, uint64_t spill_cap, const GbCounters *ctr,

@@ -118,11 +118,26 @@ struct Ctx {
     uint64_t nprimes = 0;
     DevBuf primes;
     std::vector<uint32_t> small;  // host copy of the primes <= 65536 (launch planning)
-    gb_params params = {18, 256, 4096, 0};
+    gb_params params = {18, 256, 4096, 0, 0, 0};
+    uint64_t pi2[33] = {};        // number of table primes <= 2^k
     // workspaces of the verification sequence
     DevBuf d_iv, d_rec, d_spill, d_res, d_unres, d_ctr;
     HostBuf h_iv, h_res, h_ctr;
     uint64_t spill_cap = 0;
+    DevBuf d_done;
+    HostBuf h_done;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    gb_stats stats = {};
+    double wall_khz = 100000.0;      // device wall-clock rate
+    uint64_t last_k = 0;
+    unsigned long long last_t_start = 0;
+    hipStream_t cap_stream = nullptr;   // capture stream of the batched graph
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<uint64_t> graph_key;    // every value the captured sequence bakes in
+    // bucket lists of the large primes
+    DevBuf d_bucket, d_bcount, d_chunk, d_claims, d_task;
+    HostBuf h_chunk, h_task;
+    double bcap_scale = 1.0;            // grows when a bucket overflowed
 };
 
 Ctx &ctx()
@@ -181,7 +196,9 @@ bool params_valid(const gb_params &p)
         return false;
     if (p.window != 0 && (p.window < 3 || p.window > 65536))
         return false;
-    return p.wg_per_cu <= 64;
+    if (p.bucket_log2 != 0 && (p.bucket_log2 < 17 || p.bucket_log2 > 32))
+        return false;
+    return p.wg_per_cu <= 64 && p.bucket_mib <= (1u << 20);
 }
 
 void release_all(Ctx &c)
@@ -193,10 +210,31 @@ void release_all(Ctx &c)
     c.d_res.release();
     c.d_unres.release();
     c.d_ctr.release();
+    c.d_done.release();
+    c.h_done.release();
+    c.d_bucket.release();
+    c.d_bcount.release();
+    c.d_chunk.release();
+    c.d_claims.release();
+    c.d_task.release();
+    c.h_chunk.release();
+    c.h_task.release();
+    c.graph_key.clear();
+    if (c.graph_exec)
+        (void)hipGraphExecDestroy(c.graph_exec);
+    c.graph_exec = nullptr;
+    if (c.cap_stream)
+        (void)hipStreamDestroy(c.cap_stream);
+    c.cap_stream = nullptr;
     c.h_iv.release();
     c.h_res.release();
     c.h_ctr.release();
     c.small.clear();
+    for (auto &e : c.ev)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
     c.T = 0;
     c.nprimes = 0;
     c.spill_cap = 0;
@@ -211,6 +249,9 @@ gb_status build_table(Ctx &c, uint64_t limit)
     release_all(c);
     c.device = dev;
     c.num_cu = prop.multiProcessorCount;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+        c.wall_khz = khz;
     const uint64_t T = std::max<uint64_t>(limit, 65536);
     const uint64_t nodd = (T + 1) / 2;  // odd numbers 1, 3, ..., <= T
     const uint32_t segbits = 1u << gb_table_seg_log2();
@@ -247,8 +288,8 @@ gb_status build_table(Ctx &c, uint64_t limit)
     if (e == hipSuccess)
         e = hipMemcpy(&total, d_total, 8, hipMemcpyDeviceToHost);
     seed.release();
-    counts.release();
     if (e != hipSuccess) {
+        counts.release();
         set_err("prime table build failed: %s", hipGetErrorString(e));
         release_all(c);
         return GB_EHIP;
@@ -256,13 +297,27 @@ gb_status build_table(Ctx &c, uint64_t limit)
     c.T = T;
     c.nprimes = total + 1;
     if (c.nprimes > cap) {
+        counts.release();
         set_err("prime table overflow (%llu > %llu)", (unsigned long long)c.nprimes,
                 (unsigned long long)cap);
         release_all(c);
         return GB_EHIP;
     }
+    if ((st = counts.reserve(sizeof c.pi2)) != GB_OK) {
+        release_all(c);
+        return st;
+    }
+    e = gb_launch_pow2_counts((const uint32_t *)c.primes.p, c.nprimes, (uint64_t *)counts.p, s);
+    if (e == hipSuccess)
+        e = hipMemcpy(c.pi2, counts.p, sizeof c.pi2, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        set_err("prime counts failed: %s", hipGetErrorString(e));
+        release_all(c);
+        return GB_EHIP;
+    }
     const uint64_t nsmall = std::min<uint64_t>(c.nprimes, 6542);  // pi(65536)
     c.small.resize(nsmall);
+    counts.release();
     e = hipMemcpy(c.small.data(), c.primes.p, nsmall * 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
         set_err("prime table copy failed: %s", hipGetErrorString(e));
@@ -279,14 +334,44 @@ uint64_t small_count_le(const Ctx &c, uint64_t x)
                       c.small.begin());
 }
 
+struct Round {
+    uint64_t seg_base = 0;    // global index of the round's first segment
+    uint64_t nsegs = 0;
+    uint32_t bcap = 0;        // bucket entries per segment (0: no buckets)
+    uint64_t chunk_first = 0; // chunks of this round in Plan::chunks
+    uint64_t nchunk = 0;
+    uint64_t task_first = 0;  // fill tasks of this round in Plan::tasks
+    uint64_t ntask = 0;
+    uint64_t ntiles = 0;      // fill tiles (from upper bounds; extra items exit at once)
+};
+
 struct Plan {
-    uint32_t H = 0;          // halo bits
-    uint32_t ncand = 0;      // odd candidates probed in LDS
+    uint32_t H = 0;           // halo bits
+    uint32_t ncand = 0;       // odd candidates probed in LDS
+    uint32_t lb_count = 0;    // primes sieved inside the segment kernel
+    uint64_t lb = 0;          // bucket bound: larger primes go through buckets
     uint64_t total_segs = 0;
     uint64_t total_evens = 0;
     std::vector<GbInterval> iv;
     std::vector<uint64_t> An, Bn;
+    std::vector<Round> rounds;
+    std::vector<GbChunk> chunks;
+    std::vector<GbFillTask> tasks;
+    uint64_t max_round_segs = 0;
+    uint64_t max_bucket_words = 0;
 };
+
+// pi(x) < 1.25506 x / ln x for x > 1 (Rosser and Schoenfeld 1962).
+uint64_t pi_upper(uint64_t x) { return (uint64_t)(1.25506 * (double)x / std::log((double)x)) + 16; }
+
+// Expected strikes of the primes in (lb, root] on a window of `bits` odd
+// numbers: bits * sum 1/p ~ bits * ln(ln root / ln lb) (Mertens).
+double expected_strikes(double bits, double lb, double root)
+{
+    if (root <= lb)
+        return 0.0;
+    return bits * std::log(std::log(root) / std::log(lb));
+}
 
 gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, const gb_params &pr,
                     Plan &pl)
@@ -306,12 +391,24 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
     pl.ncand = (uint32_t)(nc > 0 ? nc - 1 : 0);
     uint32_t hmax = pl.ncand ? (c.small[pl.ncand] - 1) / 2 : 0;
     pl.H = std::max<uint32_t>(32, (hmax + 31) & ~31u);
-    const uint64_t W = 1ull << pr.seg_log2;
-    const uint64_t E = W - pl.H;
+    const uint32_t lg = pr.seg_log2;
+    const uint64_t E = 1ull << lg;
+    const uint64_t Wbits = E + pl.H;
+    // bucket bound: a prime above it strikes a window at most once or twice
+    uint32_t blog = pr.bucket_log2 ? pr.bucket_log2 : lg + 1;
+    if (blog > 32)
+        blog = 32;
+    pl.lb = blog >= 32 ? 0xFFFFFFFFull : (1ull << blog);
+    pl.lb_count = (uint32_t)std::min<uint64_t>(blog >= 32 ? c.nprimes : c.pi2[blog], c.nprimes);
+    const uint64_t budget = (uint64_t)(pr.bucket_mib ? pr.bucket_mib : 4096) << 20;
+
     pl.iv.resize(k);
     pl.An.resize(k);
     pl.Bn.resize(k);
-    uint64_t seg = 0, evens = 0;
+    std::vector<double> hits(k, 0.0);   // expected bucket strikes per segment
+    std::vector<uint64_t> order;
+    order.reserve(k);
+    uint64_t evens = 0;
     for (uint64_t i = 0; i < k; ++i) {
         uint64_t a, b;
         const bool ne = normalize(AB[2 * i], AB[2 * i + 1], &a, &b);
@@ -319,54 +416,182 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
         pl.Bn[i] = b;
         GbInterval g = {};
         g.A = a;
-        g.seg_first = seg;
         if (ne) {
-            if (isqrt_u64(b) > c.T) {
+            const uint64_t root = isqrt_u64(b);
+            if (root > c.T) {
                 set_err("prime table limit %llu is below isqrt(B) = %llu for interval %llu",
-                        (unsigned long long)c.T, (unsigned long long)isqrt_u64(b),
+                        (unsigned long long)c.T, (unsigned long long)root,
                         (unsigned long long)i);
                 return GB_ERANGE;
             }
             g.nE = (b - a) / 2 + 1;
-            g.nseg = (g.nE + E - 1) / E;
+            g.nseg = (g.nE + E - 1) >> lg;
+            if (root > pl.lb && a > 2 * (uint64_t)pl.H + 2)
+                hits[i] = expected_strikes((double)Wbits, (double)pl.lb, (double)root);
         }
-        seg += g.nseg;
         evens += g.nE;
         pl.iv[i] = g;
+        order.push_back(i);
+    }
+    // segments are numbered interval by interval; intervals without bucket
+    // work come first, then by growing expected strikes per segment, so that
+    // one round groups segments of similar bucket capacity
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint64_t x, uint64_t y) { return hits[x] < hits[y]; });
+    uint64_t seg = 0;
+    for (uint64_t i : order) {
+        pl.iv[i].seg_first = seg;
+        seg += pl.iv[i].nseg;
     }
     pl.total_segs = seg;
     pl.total_evens = evens;
+
+    // rounds: first the segments without buckets, then bucketed chunks under
+    // the memory budget
+    uint64_t pos = 0;
+    size_t oi = 0;
+    {
+        Round r;
+        r.seg_base = 0;
+        while (oi < order.size() && hits[order[oi]] == 0.0) {
+            r.nsegs += pl.iv[order[oi]].nseg;
+            ++oi;
+        }
+        pos = r.nsegs;
+        if (r.nsegs)
+            pl.rounds.push_back(r);
+    }
+    Round cur;
+    cur.seg_base = pos;
+    auto close_round = [&]() {
+        if (cur.nsegs) {
+            pl.rounds.push_back(cur);
+            pl.max_round_segs = std::max(pl.max_round_segs, cur.nsegs);
+            pl.max_bucket_words = std::max(pl.max_bucket_words, cur.nsegs * (uint64_t)cur.bcap);
+        }
+        cur = Round();
+        cur.seg_base = pos;
+        cur.chunk_first = pl.chunks.size();
+        cur.task_first = pl.tasks.size();
+    };
+    cur.chunk_first = pl.chunks.size();
+    cur.task_first = pl.tasks.size();
+    const uint64_t per_tile = (uint64_t)kFillThreads * kFillPerThread;
+    for (; oi < order.size(); ++oi) {
+        const uint64_t i = order[oi];
+        const GbInterval &I = pl.iv[i];
+        const double h = hits[i] * c.bcap_scale;
+        uint64_t bcap = (uint64_t)(1.1 * h + 6.0 * std::sqrt(h) + 1024.0);
+        bcap = (bcap + 63) & ~63ull;
+        if (bcap > 0xFFFFFFF0ull) {
+            set_err("bucket capacity per segment out of range");
+            return GB_ENOMEM;
+        }
+        // chunk length: every chunk fits a round on its own within the budget
+        uint64_t cmax = budget / (bcap * 4);
+        if (cmax < 1) {
+            set_err("bucket budget of %llu MiB is below one segment's bucket",
+                    (unsigned long long)(budget >> 20));
+            return GB_ENOMEM;
+        }
+        cmax = std::min<uint64_t>(cmax, 1u << 16);
+        for (uint64_t s0 = 0; s0 < I.nseg; s0 += cmax) {
+            const uint64_t ns = std::min<uint64_t>(cmax, I.nseg - s0);
+            GbChunk ch = {};
+            ch.nseg = (uint32_t)ns;
+            const uint64_t n0 = I.A + 2 * E * s0;                 // first even of the chunk
+            const uint64_t last = s0 + ns - 1;
+            const uint64_t nl = I.A + 2 * E * last;               // first even of its last segment
+            const uint64_t cl = std::min<uint64_t>(E, I.nE - E * last);
+            const uint64_t top = nl + 2 * cl - 5;                 // largest q read
+            ch.Q0 = n0 - 1 - 2ull * pl.H;                         // n0 > 2H + 2 here
+            ch.dmax = (top - ch.Q0) / 2;
+            ch.p_root = 0;                                        // set on the device
+            const uint64_t root = isqrt_u64(top);
+            const uint64_t pub = std::min<uint64_t>(pi_upper(root), c.nprimes);
+            // one task per prime band (2^b, 2^(b+1)] that reaches below the root
+            std::vector<GbFillTask> ts;
+            uint64_t tiles = 0;
+            for (uint32_t bb = blog; bb < 32 && (1ull << bb) < root; ++bb) {
+                const uint64_t pf = c.pi2[bb];
+                const uint64_t pe = std::min<uint64_t>(c.pi2[bb + 1], pub);
+                if (pe <= pf)
+                    continue;
+                GbFillTask t = {};
+                t.p_first = (uint32_t)pf;
+                t.np = (uint32_t)(pe - pf);
+                t.sl_log2 = bb + 3;   // kFillStrikes * 2^b bits
+                t.nsub = (uint32_t)(((ch.dmax + 1) + (1ull << t.sl_log2) - 1) >> t.sl_log2);
+                t.tile_first = tiles;
+                tiles += ((uint64_t)t.np * t.nsub + per_tile - 1) / per_tile;
+                ts.push_back(t);
+            }
+            if (tiles > (1ull << 30)) {
+                set_err("bucket fill of one chunk needs %llu tiles", (unsigned long long)tiles);
+                return GB_ENOMEM;
+            }
+            const uint32_t ncap = (uint32_t)std::max<uint64_t>(cur.bcap, bcap);
+            if (cur.nsegs && ((cur.nsegs + ns) * (uint64_t)ncap * 4 > budget ||
+                              cur.ntiles + tiles > (1ull << 30)))
+                close_round();
+            cur.bcap = (uint32_t)std::max<uint64_t>(cur.bcap, bcap);
+            ch.seg_first = I.seg_first + s0;
+            const uint32_t cidx = (uint32_t)(pl.chunks.size() - cur.chunk_first);
+            for (GbFillTask &t : ts) {
+                t.chunk = cidx;
+                t.tile_first += cur.ntiles;
+                pl.tasks.push_back(t);
+                ++cur.ntask;
+            }
+            cur.ntiles += tiles;
+            cur.nsegs += ns;
+            pos += ns;
+            ++cur.nchunk;
+            pl.chunks.push_back(ch);
+        }
+    }
+    close_round();
+    for (const Round &r : pl.rounds)
+        pl.max_round_segs = std::max(pl.max_round_segs, r.nsegs);
     return GB_OK;
 }
 
-// One pass of the launch sequence; the caller retries when spills overflow.
-gb_status run_once(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr, hipStream_t s,
-                   uint64_t *spills_out)
+// The kernels of one verification, in stream order:
+//   reset -> per round: [bucket reset -> bucket fill ->] persistent
+//   sieve+probe -> Phase 2 -> reduce -> unresolved list.
+// Every kernel reads its sizes from device memory (counters, descriptors), so
+// the sequence needs no host round trip and can be captured as a graph.
+gb_status enqueue_kernels(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr,
+                          uint32_t grid, hipStream_t s, bool mark_probe)
 {
     const uint64_t k = pl.iv.size();
-    GB_TRY(c.d_iv.reserve(k * sizeof(GbInterval)));
-    GB_TRY(c.d_rec.reserve(std::max<uint64_t>(pl.total_segs, 1) * sizeof(GbSegRecord)));
-    GB_TRY(c.d_res.reserve(k * sizeof(GbIvResult)));
-    GB_TRY(c.d_ctr.reserve(sizeof(GbCounters)));
-    GB_TRY(c.h_iv.reserve(k * sizeof(GbInterval)));
-    GB_TRY(c.h_res.reserve(k * sizeof(GbIvResult)));
-    GB_TRY(c.h_ctr.reserve(sizeof(GbCounters)));
-    GB_TRY(c.d_spill.reserve(c.spill_cap * sizeof(GbSpill)));
-    GB_TRY(c.d_unres.reserve(c.spill_cap * sizeof(uint64_t)));
-
-    std::memcpy(c.h_iv.p, pl.iv.data(), k * sizeof(GbInterval));
-    GB_HIP(hipMemcpyAsync(c.d_iv.p, c.h_iv.p, k * sizeof(GbInterval), hipMemcpyHostToDevice, s));
     GbCounters *ctr = (GbCounters *)c.d_ctr.p;
-    GB_HIP(gb_launch_reset(ctr, s));
-
-    if (pl.total_segs) {
-        int occ = 0;
-        GB_HIP(gb_probe_occupancy((int)pr.seg_log2, (int)pr.wg_size, &occ));
-        if (occ < 1)
-            occ = 1;
-        if (pr.wg_per_cu)
-            occ = std::min<int>(occ, (int)pr.wg_per_cu);
-        const uint64_t grid = std::min<uint64_t>(pl.total_segs, (uint64_t)c.num_cu * occ);
+    unsigned long long *claims = (unsigned long long *)c.d_claims.p;
+    GB_HIP(gb_launch_reset(ctr, (GbIvDone *)c.d_done.p, (uint32_t)k, claims,
+                           (uint32_t)pl.rounds.size(), s));
+    GB_HIP(gb_launch_chunk_roots((const uint32_t *)c.primes.p, c.nprimes, (GbChunk *)c.d_chunk.p,
+                                 pl.chunks.size(), s));
+    if (mark_probe)
+        GB_HIP(hipEventRecord(c.ev[1], s));
+    for (size_t ri = 0; ri < pl.rounds.size(); ++ri) {
+        const Round &r = pl.rounds[ri];
+        if (r.bcap) {
+            GB_HIP(gb_launch_bucket_reset((uint32_t *)c.d_bcount.p, r.nsegs, nullptr, s));
+            GbBucketArgs b = {};
+            b.primes = (const uint32_t *)c.primes.p;
+            b.chunk = (const GbChunk *)c.d_chunk.p + r.chunk_first;
+            b.task = (const GbFillTask *)c.d_task.p + r.task_first;
+            b.ntask = (uint32_t)r.ntask;
+            b.log2e = pr.seg_log2;
+            b.H = pl.H;
+            b.bcap = r.bcap;
+            b.ntiles = r.ntiles;
+            b.seg_base = r.seg_base;
+            b.bucket = (uint32_t *)c.d_bucket.p;
+            b.bcount = (uint32_t *)c.d_bcount.p;
+            if (r.ntask && r.ntiles)
+                GB_HIP(gb_launch_bucket_fill(b, (uint32_t)r.ntiles, s));
+        }
         GbProbeArgs a = {};
         a.primes = (const uint32_t *)c.primes.p;
         a.nprimes = c.nprimes;
@@ -374,13 +599,24 @@ gb_status run_once(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr, 
         a.k = (uint32_t)k;
         a.H = pl.H;
         a.ncand = pl.ncand;
-        a.total_segs = pl.total_segs;
+        a.lb_count = r.bcap ? pl.lb_count : (uint32_t)c.nprimes;
+        a.seg_base = r.seg_base;
+        a.nsegs = r.nsegs;
         a.rec = (GbSegRecord *)c.d_rec.p;
         a.spill = (GbSpill *)c.d_spill.p;
         a.spill_cap = c.spill_cap;
         a.ctr = ctr;
-        GB_HIP(gb_launch_probe((int)pr.seg_log2, (int)pr.wg_size, (uint32_t)grid, a, s));
+        a.claim = claims + ri;
+        a.done = (GbIvDone *)c.d_done.p;
+        a.bucket = (const uint32_t *)c.d_bucket.p;
+        a.bcount = (const uint32_t *)c.d_bcount.p;
+        a.bcap = r.bcap;
+        a.bover = (unsigned long long *)&ctr->pad[0];
+        const uint32_t g = (uint32_t)std::min<uint64_t>(grid, r.nsegs);
+        GB_HIP(gb_launch_probe((int)pr.seg_log2, (int)pr.wg_size, g, a, s));
     }
+    if (mark_probe)
+        GB_HIP(hipEventRecord(c.ev[2], s));
     GB_HIP(gb_launch_phase2((const uint32_t *)c.primes.p, c.nprimes, (uint64_t)pl.ncand + 1,
                             (GbSpill *)c.d_spill.p, c.spill_cap, ctr, (uint32_t)c.num_cu * 4, s));
     GB_HIP(gb_launch_reduce((const GbInterval *)c.d_iv.p, (uint32_t)k, (const GbSegRecord *)c.d_rec.p,
@@ -388,15 +624,173 @@ gb_status run_once(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr, 
                             (GbIvResult *)c.d_res.p, s));
     GB_HIP(gb_launch_unres_emit((const GbSpill *)c.d_spill.p, c.spill_cap, ctr, P_max,
                                 (uint64_t *)c.d_unres.p, (uint32_t)c.num_cu * 2, s));
+    return GB_OK;
+}
+
+void drop_graph(Ctx &c)
+{
+    if (c.graph_exec)
+        (void)hipGraphExecDestroy(c.graph_exec);
+    c.graph_exec = nullptr;
+    c.graph_key.clear();
+}
+
+// Every value the captured sequence bakes into kernel arguments.
+std::vector<uint64_t> graph_key(const Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr,
+                                uint32_t grid)
+{
+    std::vector<uint64_t> key = {
+        (uint64_t)c.primes.p, (uint64_t)c.d_iv.p, (uint64_t)c.d_rec.p, (uint64_t)c.d_spill.p,
+        (uint64_t)c.d_unres.p, (uint64_t)c.d_res.p, (uint64_t)c.d_ctr.p, (uint64_t)c.d_done.p,
+        (uint64_t)c.d_bucket.p, (uint64_t)c.d_bcount.p, (uint64_t)c.d_chunk.p,
+        (uint64_t)c.d_claims.p, (uint64_t)c.d_task.p, pl.chunks.size(), c.nprimes, pl.iv.size(),
+        c.spill_cap, P_max, pl.H, pl.ncand,
+        pl.lb_count, pr.seg_log2, pr.wg_size, grid, (uint64_t)c.num_cu};
+    for (const Round &r : pl.rounds) {
+        key.push_back(r.seg_base);
+        key.push_back(r.nsegs);
+        key.push_back(r.bcap);
+        key.push_back(r.chunk_first);
+        key.push_back(r.nchunk);
+        key.push_back(r.task_first);
+        key.push_back(r.ntask);
+        key.push_back(r.ntiles);
+    }
+    return key;
+}
+
+// Capture the launch sequence on the library's own stream (the legacy default
+// stream cannot be captured) and instantiate it; reused while the key holds.
+gb_status capture_graph(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr,
+                        uint32_t grid, const std::vector<uint64_t> &key)
+{
+    if (c.graph_exec && c.graph_key == key)
+        return GB_OK;
+    drop_graph(c);
+    if (!c.cap_stream)
+        GB_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+    GB_HIP(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
+    gb_status st = enqueue_kernels(c, pl, P_max, pr, grid, c.cap_stream, false);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(c.cap_stream, &graph);
+    if (st != GB_OK) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) {
+        set_err("graph capture failed: %s", hipGetErrorString(e));
+        return GB_EHIP;
+    }
+    e = hipGraphInstantiate(&c.graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        c.graph_exec = nullptr;
+        set_err("graph instantiation failed: %s", hipGetErrorString(e));
+        return GB_EHIP;
+    }
+    c.graph_key = key;
+    return GB_OK;
+}
+
+// One pass of the launch sequence; the caller retries when a capacity
+// (spill list, bucket) overflowed.
+gb_status run_once(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr, hipStream_t s,
+                   bool use_graph, uint64_t *spills_out, uint64_t *bover_out)
+{
+    const uint64_t k = pl.iv.size();
+    const uint64_t nr = std::max<size_t>(pl.rounds.size(), 1);
+    GB_TRY(c.d_iv.reserve(k * sizeof(GbInterval)));
+    GB_TRY(c.d_rec.reserve(std::max<uint64_t>(pl.total_segs, 1) * sizeof(GbSegRecord)));
+    GB_TRY(c.d_res.reserve(k * sizeof(GbIvResult)));
+    GB_TRY(c.d_ctr.reserve(sizeof(GbCounters)));
+    GB_TRY(c.d_done.reserve(k * sizeof(GbIvDone)));
+    GB_TRY(c.d_claims.reserve(nr * 8));
+    GB_TRY(c.d_chunk.reserve(std::max<size_t>(pl.chunks.size(), 1) * sizeof(GbChunk)));
+    GB_TRY(c.h_chunk.reserve(std::max<size_t>(pl.chunks.size(), 1) * sizeof(GbChunk)));
+    GB_TRY(c.d_task.reserve(std::max<size_t>(pl.tasks.size(), 1) * sizeof(GbFillTask)));
+    GB_TRY(c.h_task.reserve(std::max<size_t>(pl.tasks.size(), 1) * sizeof(GbFillTask)));
+    GB_TRY(c.d_bcount.reserve(std::max<uint64_t>(pl.max_round_segs, 1) * 4));
+    GB_TRY(c.d_bucket.reserve(std::max<uint64_t>(pl.max_bucket_words, 1) * 4));
+    GB_TRY(c.h_iv.reserve(k * sizeof(GbInterval)));
+    GB_TRY(c.h_res.reserve(k * sizeof(GbIvResult)));
+    GB_TRY(c.h_ctr.reserve(sizeof(GbCounters)));
+    GB_TRY(c.h_done.reserve(k * sizeof(GbIvDone)));
+    GB_TRY(c.d_spill.reserve(c.spill_cap * sizeof(GbSpill)));
+    GB_TRY(c.d_unres.reserve(c.spill_cap * sizeof(uint64_t)));
+    for (auto &e : c.ev)
+        if (!e)
+            GB_HIP(hipEventCreate(&e));
+
+    uint32_t grid = 0;
+    if (pl.total_segs) {
+        int occ = 0;
+        GB_HIP(gb_probe_occupancy((int)pr.seg_log2, (int)pr.wg_size, &occ));
+        if (occ < 1)
+            occ = 1;
+        if (pr.wg_per_cu)
+            occ = std::min<int>(occ, (int)pr.wg_per_cu);
+        grid = (uint32_t)std::min<uint64_t>(pl.total_segs, (uint64_t)c.num_cu * occ);
+    }
+    std::memcpy(c.h_iv.p, pl.iv.data(), k * sizeof(GbInterval));
+    GB_HIP(hipMemcpyAsync(c.d_iv.p, c.h_iv.p, k * sizeof(GbInterval), hipMemcpyHostToDevice, s));
+    if (!pl.chunks.empty()) {
+        std::memcpy(c.h_chunk.p, pl.chunks.data(), pl.chunks.size() * sizeof(GbChunk));
+        GB_HIP(hipMemcpyAsync(c.d_chunk.p, c.h_chunk.p, pl.chunks.size() * sizeof(GbChunk),
+                              hipMemcpyHostToDevice, s));
+    }
+    if (!pl.tasks.empty()) {
+        std::memcpy(c.h_task.p, pl.tasks.data(), pl.tasks.size() * sizeof(GbFillTask));
+        GB_HIP(hipMemcpyAsync(c.d_task.p, c.h_task.p, pl.tasks.size() * sizeof(GbFillTask),
+                              hipMemcpyHostToDevice, s));
+    }
+    GB_HIP(hipEventRecord(c.ev[0], s));
+    if (use_graph) {
+        const std::vector<uint64_t> key = graph_key(c, pl, P_max, pr, grid);
+        GB_TRY(capture_graph(c, pl, P_max, pr, grid, key));
+        GB_HIP(hipGraphLaunch(c.graph_exec, s));
+    } else {
+        GB_TRY(enqueue_kernels(c, pl, P_max, pr, grid, s, true));
+    }
     GB_HIP(hipMemcpyAsync(c.h_res.p, c.d_res.p, k * sizeof(GbIvResult), hipMemcpyDeviceToHost, s));
-    GB_HIP(hipMemcpyAsync(c.h_ctr.p, ctr, sizeof(GbCounters), hipMemcpyDeviceToHost, s));
+    GB_HIP(hipMemcpyAsync(c.h_ctr.p, c.d_ctr.p, sizeof(GbCounters), hipMemcpyDeviceToHost, s));
+    GB_HIP(hipMemcpyAsync(c.h_done.p, c.d_done.p, k * sizeof(GbIvDone), hipMemcpyDeviceToHost, s));
+    GB_HIP(hipEventRecord(c.ev[3], s));
     GB_HIP(hipStreamSynchronize(s));
-    *spills_out = ((GbCounters *)c.h_ctr.p)->spills;
+    const GbCounters *hc = (const GbCounters *)c.h_ctr.p;
+    *spills_out = hc->spills;
+    *bover_out = hc->pad[0];
+    float total = 0;
+    GB_HIP(hipEventElapsedTime(&total, c.ev[0], c.ev[3]));
+    const GbIvDone *hd = (const GbIvDone *)c.h_done.p;
+    unsigned long long tmax = hc->t_start;
+    for (uint64_t i = 0; i < k; ++i)
+        tmax = std::max(tmax, hd[i].t_done);
+    double probe = (double)(tmax - hc->t_start) / c.wall_khz;
+    if (!use_graph) {
+        float pm = 0;
+        GB_HIP(hipEventElapsedTime(&pm, c.ev[1], c.ev[2]));
+        probe = pm;
+    }
+    c.last_k = k;
+    c.last_t_start = hc->t_start;
+    gb_stats &st = c.stats;
+    st.probe_ms = probe;
+    st.total_ms = total;
+    st.segments = pl.total_segs;
+    st.evens = pl.total_evens;
+    st.spills = *spills_out;
+    st.grid = grid;
+    st.wg_size = pr.wg_size;
+    st.seg_log2 = pr.seg_log2;
+    st.halo_bits = pl.H;
+    st.ncand = pl.ncand;
+    st.intervals = k;
     return GB_OK;
 }
 
 gb_status verify_many(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, hipStream_t s,
-                      gb_result *outs)
+                      gb_result *outs, bool use_graph)
 {
     if (k == 0)
         return GB_OK;
@@ -410,20 +804,25 @@ gb_status verify_many(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, hi
     }
     GB_TRY(use_device(c));
     const gb_params pr = c.params;
-    Plan pl;
-    GB_TRY(make_plan(c, AB, k, P_max, pr, pl));
     if (c.spill_cap == 0)
         c.spill_cap = 1 << 16;
-    uint64_t spills = 0;
+    Plan pl;
+    uint64_t spills = 0, bover = 0;
     for (int attempt = 0;; ++attempt) {
-        GB_TRY(run_once(c, pl, P_max, pr, s, &spills));
-        if (spills <= c.spill_cap)
+        pl = Plan();
+        GB_TRY(make_plan(c, AB, k, P_max, pr, pl));
+        GB_TRY(run_once(c, pl, P_max, pr, s, use_graph, &spills, &bover));
+        if (spills <= c.spill_cap && bover == 0)
             break;
-        if (attempt >= 3) {
-            set_err("spill list kept overflowing (%llu entries)", (unsigned long long)spills);
+        if (attempt >= 4) {
+            set_err("capacities kept overflowing (spills %llu, bucket %llu)",
+                    (unsigned long long)spills, (unsigned long long)bover);
             return GB_ENOMEM;
         }
-        c.spill_cap = spills + spills / 4 + 1024;
+        if (spills > c.spill_cap)
+            c.spill_cap = spills + spills / 4 + 1024;
+        if (bover)
+            c.bcap_scale *= 2.0;   // a bucket overflowed: rerun with larger buckets
     }
     const GbIvResult *res = (const GbIvResult *)c.h_res.p;
     gb_status status = GB_OK;
@@ -457,6 +856,8 @@ gb_status verify_many(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, hi
 }
 
 }  // namespace
+
+void gb_internal_set_error(const char *msg) { g_err = msg ? msg : ""; }
 
 extern "C" {
 
@@ -511,7 +912,7 @@ gb_status gb_verify_range(uint64_t A, uint64_t B, uint64_t P_max, void *stream, 
         return GB_EINVAL;
     }
     const uint64_t AB[2] = {A, B};
-    return verify_many(c, AB, 1, P_max, (hipStream_t)stream, out);
+    return verify_many(c, AB, 1, P_max, (hipStream_t)stream, out, false);
 }
 
 gb_status gb_verify_batch(const uint64_t *AB, uint64_t k, uint64_t P_max, void *stream,
@@ -520,7 +921,7 @@ gb_status gb_verify_batch(const uint64_t *AB, uint64_t k, uint64_t P_max, void *
     Ctx &c = ctx();
     std::lock_guard<std::mutex> lk(c.mu);
     g_err.clear();
-    return verify_many(c, AB, k, P_max, (hipStream_t)stream, outs);
+    return verify_many(c, AB, k, P_max, (hipStream_t)stream, outs, true);
 }
 
 gb_status gb_set_params(const gb_params *p)
@@ -556,8 +957,8 @@ gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream, gb_p
     g_err.clear();
     GB_TRY(use_device(c));
     uint64_t An, Bn;
-    if (!normalize(A, B, &An, &Bn) || (Bn - An) / 2 + 1 > (1ull << 31)) {
-        set_err("calibration range must be non-empty and hold at most 2^31 evens");
+    if (!normalize(A, B, &An, &Bn) || (Bn - An) / 2 + 1 > (1ull << 36)) {
+        set_err("calibration range must be non-empty and hold at most 2^36 evens");
         return GB_EINVAL;
     }
     const gb_params saved = c.params;
@@ -571,7 +972,7 @@ gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream, gb_p
     for (uint32_t lg : logs)
         for (uint32_t wg : wgs)
             for (uint32_t win : wins) {
-                gb_params p = {lg, wg, win, 0};
+                gb_params p = {lg, wg, win, 0, saved.bucket_log2, saved.bucket_mib};
                 int occ = 0;
                 if (gb_probe_occupancy((int)lg, (int)wg, &occ) != hipSuccess || occ < 1) {
                     (void)hipGetLastError();
@@ -582,7 +983,7 @@ gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream, gb_p
                 double tmin = 1e300;
                 for (int rep = 0; rep < 2; ++rep) {
                     const auto t0 = std::chrono::steady_clock::now();
-                    gb_status st = verify_many(c, AB, 1, P_max, s, &r);
+                    gb_status st = verify_many(c, AB, 1, P_max, s, &r, false);
                     const auto t1 = std::chrono::steady_clock::now();
                     if (st != GB_OK && st != GB_ETRUNC) {
                         c.params = saved;
@@ -625,6 +1026,35 @@ gb_status gb_release(void)
     if (c.device >= 0)
         (void)hipSetDevice(c.device);
     release_all(c);
+    return GB_OK;
+}
+
+gb_status gb_last_stats(gb_stats *out)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    g_err.clear();
+    if (!out) {
+        set_err("null stats");
+        return GB_EINVAL;
+    }
+    *out = c.stats;
+    return GB_OK;
+}
+
+gb_status gb_last_latencies(double *ms, uint64_t k)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    g_err.clear();
+    if (!ms || k != c.last_k || !c.h_done.p) {
+        set_err("latency buffer must hold exactly the last call's %llu intervals",
+                (unsigned long long)c.last_k);
+        return GB_EINVAL;
+    }
+    const GbIvDone *hd = (const GbIvDone *)c.h_done.p;
+    for (uint64_t i = 0; i < k; ++i)
+        ms[i] = hd[i].t_done ? (double)(hd[i].t_done - c.last_t_start) / c.wall_khz : 0.0;
     return GB_OK;
 }
 

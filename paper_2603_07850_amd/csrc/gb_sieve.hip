@@ -5,20 +5,27 @@
 // probe every even n of the segment against the ascending candidate primes
 // (Phase 1, Sec. 3.3).
 //
-// Geometry of one segment (W = 2^LOG2W bits of LDS, halo H bits, E = W - H):
+// Geometry of one segment (E = 2^LOG2E evens, halo H bits, window W = E + H
+// bits of LDS):
 //   evens    n = n0 + 2i, 0 <= i < cnt <= E
 //   bit b    odd q = q_lo + 2b,  q_lo = n0 - 1 - 2H   (q_lo may be negative
 //            for the first segments; every q <= 1 is marked composite)
 //   then     bit(n0 + 2i - p) = i + H - (p - 1)/2, so every candidate
 //            p <= 2H + 1 reads inside the window.
+// Segment s of an interval starts E*s bits after segment 0, so consecutive
+// windows overlap by H bits and a window bit d of the interval belongs to
+// segment d >> LOG2E (and to the previous one when d mod E < H).
 //
 // Sieve (every q is odd):
 //   * primes 3..31   periodic 32-bit word masks, one word write per 32 odds;
 //   * primes >= 37   strided clears from max(p^2, first multiple in the
-//                    window) with LDS atomic AND; primes up to W/NT are
+//                    window) with LDS atomic AND; primes up to E/NT are
 //                    cleared cooperatively by the whole workgroup (each thread
 //                    keeps one bit position, so its mask is loop-invariant),
-//                    larger ones one prime per thread.
+//                    larger ones one prime per thread;
+//   * primes above the bucket bound (when the launch has buckets) are not
+//                    visited here: the bucket-fill kernel has listed the
+//                    window bits they strike, and the segment clears them.
 // Probe (bit-parallel): a thread owns 32 consecutive evens.  For candidate p
 // the 32 bits q = n - p of those evens are 32 consecutive window bits, so one
 // funnel shift of two LDS words tests p against all 32 evens at once; hits are
@@ -32,7 +39,12 @@
 namespace {
 
 constexpr uint32_t kPre[10] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
+constexpr uint32_t kHaloMax = 32768;  // largest halo: candidates up to 65536
 constexpr uint32_t kFirstStrided = 11;  // primes[11] == 37
+
+// The prime table seen through the constant address space: loads with a
+// uniform index compile to scalar loads.
+typedef const __attribute__((address_space(4))) uint32_t *cprime_t;
 
 __host__ __device__ constexpr uint32_t word_pattern(uint32_t p)
 {
@@ -86,13 +98,13 @@ __device__ __forceinline__ bool small_prime_35(int64_t q)
            q == 29 || q == 31;
 }
 
-template <int LOG2W, int NT>
+template <int LOG2E, int NT>
 __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
 {
-    constexpr uint32_t W = 1u << LOG2W;
-    constexpr uint32_t NW = W / 32;
+    constexpr uint64_t E = 1ull << LOG2E;
+    constexpr uint32_t NW = (uint32_t)((E + kHaloMax) / 32);
     constexpr uint32_t NWAVE = NT / 64;
-    constexpr uint32_t PS = W / NT;  // cooperative-clear bound
+    constexpr uint32_t PS = (uint32_t)(E / NT);  // cooperative-clear bound
     __shared__ uint32_t bits[NW];
     __shared__ unsigned long long sh_seg;
     __shared__ unsigned long long red_sum[NWAVE];
@@ -105,16 +117,17 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
     const uint32_t wave = tid >> 6;
     const uint32_t H = a.H;
     const uint32_t H32 = H >> 5;
-    const uint64_t E = W - H;
+    const uint32_t NWr = (uint32_t)((E + H) >> 5);  // window words in use
     const uint32_t *__restrict__ primes = a.primes;
 
     for (;;) {
         if (tid == 0)
-            sh_seg = atomicAdd(&a.ctr->claim, 1ull);
+            sh_seg = atomicAdd(a.claim, 1ull);
         __syncthreads();
-        const uint64_t seg = sh_seg;
-        if (seg >= a.total_segs)
+        const uint64_t claim = sh_seg;
+        if (claim >= a.nsegs)
             break;
+        const uint64_t seg = a.seg_base + claim;
 
         // ---- locate the interval and the segment geometry (uniform) ----
         uint32_t lo = 0, hi = a.k - 1;
@@ -136,7 +149,8 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
         const uint64_t qlo = n0 - 1 - 2ull * H;     // valid when !neg
         const uint64_t qneg = 2ull * H + 1 - n0;    // valid when neg
         const uint64_t qhi = n0 + 2ull * cnt - 5;   // largest q any n of the segment needs
-        const uint32_t nsieve = count_le(primes, a.nprimes, gb_isqrt64(qhi));
+        const uint32_t nroot = count_le(primes, a.nprimes, gb_isqrt64(qhi));
+        const uint32_t nsieve = nroot < a.lb_count ? nroot : a.lb_count;  // primes cleared here
         const uint32_t ncoop = count_le(primes, a.nprimes, PS);
 
         // ---- presieve: periodic masks of 3..31 ----
@@ -151,7 +165,7 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
                 ph[i] = (beta + p - (32u * tid) % p) % p;   // (beta - 32w) mod p at w = tid
                 dec[i] = (32u * NT) % p;
             }
-            for (uint32_t w = tid; w < NW; w += NT) {
+            for (uint32_t w = tid; w < NWr; w += NT) {
                 uint32_t m = 0;
 #pragma unroll
                 for (int i = 0; i < 10; ++i) {
@@ -179,7 +193,7 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
         }
         __syncthreads();
 
-        // ---- strided clears, cooperative tier: 37 <= p <= W/NT ----
+        // ---- strided clears, cooperative tier: 37 <= p <= E/NT ----
         const uint32_t wend = (weff + 31) >> 5;
         const uint32_t coop_end = ncoop < nsieve ? ncoop : nsieve;
         for (uint32_t i = kFirstStrided; i < coop_end; ++i) {
@@ -192,7 +206,7 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
                     atomicAnd(&bits[w], mask);
             }
         }
-        // ---- strided clears, one prime per thread: W/NT < p <= isqrt(q_hi) ----
+        // ---- strided clears, one prime per thread: E/NT < p <= min(isqrt(q_hi), bound) ----
         {
             const uint32_t first = coop_end > kFirstStrided ? coop_end : kFirstStrided;
             for (uint32_t i = first + tid; i < nsieve; i += NT) {
@@ -206,9 +220,29 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
                 }
             }
         }
+        // ---- bucket drain: the bits struck by primes above the bound ----
+        if (a.bcap) {
+            const uint64_t rel = seg - a.seg_base;
+            const uint32_t c = a.bcount[rel];
+            const uint32_t lim = c < a.bcap ? c : a.bcap;
+            const uint32_t *__restrict__ bk = a.bucket + rel * a.bcap;
+            for (uint32_t e = tid; e < lim; e += NT) {
+                const uint32_t o = bk[e];
+                atomicAnd(&bits[o >> 5], ~(1u << (o & 31)));
+            }
+            if (tid == 0 && c > a.bcap)
+                atomicMax(a.bover, (unsigned long long)c);
+        }
         __syncthreads();
 
         // ---- probe ----
+        // Candidates are read through the constant address space so that the
+        // uniform index k becomes scalar loads; the per-candidate work is then
+        // one LDS pair read, a funnel shift and four integer ops per lane.
+        const cprime_t cp = (cprime_t)primes;
+        const uint32_t ncand = a.ncand;
+        const uint32_t ngrp = ncand >> 2;
+        const char *lds = (const char *)bits;
         const uint32_t nblk = (cnt + 31) >> 5;
         uint64_t sum = 0;
         uint32_t nres = 0;
@@ -232,27 +266,88 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
                     u &= ~1u;
             }
             const uint32_t u0 = u;
-            const uint32_t wb = (act ? j : 0) + H32;
-            uint32_t lastp = 0, lasth = 0;
-            for (uint32_t k = 1; k <= a.ncand; ++k) {
-                if (__ballot(u != 0) == 0)
-                    break;
-                const uint32_t p = primes[k];
-                const uint32_t h = p >> 1;
-                const uint32_t w = wb - ((h + 31) >> 5);
-                const uint32_t x = __builtin_amdgcn_alignbit(bits[w + 1], bits[w], (0u - h) & 31);
-                const uint32_t hit = x & u;
-                if (hit) {
+            const uint32_t base4 = ((act ? j : 0) + H32) * 4;  // byte address of the lane's word
+            uint32_t sum32 = 0;   // < 32 * 2^16 per block
+            uint32_t lastg = 0;   // first candidate of the last group with a hit
+            uint32_t ulast = 0;   // open evens at the start of that group
+            uint32_t k = 1;
+            // candidates of the next group are loaded one group ahead
+            uint32_t pn[4];
+#pragma unroll
+            for (uint32_t t = 0; t < 4; ++t)
+                pn[t] = cp[1 + t < ncand ? 1 + t : ncand];
+            for (uint32_t g = 0; g < ngrp; ++g, k += 4) {
+                const uint32_t ustart = u;
+                uint32_t pc[4];
+#pragma unroll
+                for (uint32_t t = 0; t < 4; ++t) {
+                    pc[t] = pn[t];
+                    const uint32_t kn = k + 4 + t;
+                    pn[t] = cp[kn < ncand ? kn : ncand];
+                }
+#pragma unroll
+                for (uint32_t t = 0; t < 4; ++t) {
+                    const uint32_t p = pc[t];
+                    const uint32_t h = p >> 1;
+                    const uint32_t addr = base4 - (((h + 31) >> 5) << 2);
+                    const uint32_t lo = *(const uint32_t *)(lds + addr);
+                    const uint32_t hi = *(const uint32_t *)(lds + addr + 4);
+                    const uint32_t hit = __builtin_amdgcn_alignbit(hi, lo, (0u - h) & 31) & u;
                     u ^= hit;
-                    sum += (uint64_t)p * (uint32_t)__popc(hit);
-                    lastp = p;
-                    lasth = hit;
+                    sum32 = __umul24(p, (uint32_t)__popc(hit)) + sum32;
+                }
+                const bool any = u != ustart;
+                lastg = any ? k : lastg;
+                ulast = any ? ustart : ulast;
+                if (__ballot(u != 0) == 0) {
+                    k += 4;
+                    break;
                 }
             }
+            if (__ballot(u != 0) != 0) {
+                for (; k <= ncand; ++k) {
+                    const uint32_t ustart = u;
+                    const uint32_t p = cp[k];
+                    const uint32_t h = p >> 1;
+                    const uint32_t addr = base4 - (((h + 31) >> 5) << 2);
+                    const uint32_t lo = *(const uint32_t *)(lds + addr);
+                    const uint32_t hi = *(const uint32_t *)(lds + addr + 4);
+                    const uint32_t hit = __builtin_amdgcn_alignbit(hi, lo, (0u - h) & 31) & u;
+                    u ^= hit;
+                    sum32 = __umul24(p, (uint32_t)__popc(hit)) + sum32;
+                    const bool any = u != ustart;
+                    lastg = any ? k : lastg;
+                    ulast = any ? ustart : ulast;
+                    if (__ballot(u != 0) == 0)
+                        break;
+                }
+            }
+            sum += sum32;
             nres += (uint32_t)(__popc(u0) - __popc(u));
-            if (lastp > bestp) {
-                bestp = lastp;
-                bestn = n0 + 64ull * j + 2ull * (uint32_t)(__ffs(lasth) - 1);
+            // Replay the last group with a hit: its last hitting candidate is
+            // the block's largest p_min, and the lowest bit of that hit is the
+            // smallest n attaining it.  Every candidate replayed here was also
+            // tested above, so the replay reproduces the same hits.
+            if (lastg) {
+                uint32_t uu = ulast, lastp = 0, lasth = 0;
+                const uint32_t kend = lastg + 3 < ncand ? lastg + 3 : ncand;
+                for (uint32_t kk = lastg; kk <= kend && uu; ++kk) {
+                    const uint32_t p = primes[kk];
+                    const uint32_t h = p >> 1;
+                    const uint32_t addr = base4 - (((h + 31) >> 5) << 2);
+                    const uint32_t lo = *(const uint32_t *)(lds + addr);
+                    const uint32_t hi = *(const uint32_t *)(lds + addr + 4);
+                    const uint32_t hit = __builtin_amdgcn_alignbit(hi, lo, (0u - h) & 31) & uu;
+                    if (hit) {
+                        uu ^= hit;
+                        lastp = p;
+                        lasth = hit;
+                    }
+                }
+                if (lastp > bestp) {
+                    bestp = lastp;
+                    bestn = n0 + 64ull * j + 2ull * (uint32_t)(__ffs(lasth) - 1);
+                }
             }
             while (u) {
                 const uint32_t b = __ffs(u) - 1;
@@ -303,28 +398,50 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
             r.max_n = bp ? bn : 0;
             r.pad = 0;
             a.rec[seg] = r;
+            // the interval is complete when its last segment record is written
+            __threadfence();
+            if (atomicAdd(&a.done[ivx].segs_done, 1ull) + 1 == I.nseg)
+                a.done[ivx].t_done = wall_clock64();
         }
         __syncthreads();
     }
 }
 
-__global__ void reset_kernel(GbCounters *ctr)
+__global__ void reset_kernel(GbCounters *ctr, GbIvDone *done, uint32_t k,
+                             unsigned long long *claims, uint32_t nclaims)
 {
-    if (threadIdx.x < sizeof(GbCounters) / 8)
-        reinterpret_cast<unsigned long long *>(ctr)[threadIdx.x] = 0;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < sizeof(GbCounters) / 8)
+        reinterpret_cast<unsigned long long *>(ctr)[t] = t == 2 ? wall_clock64() : 0;
+    for (uint32_t i = t; i < nclaims; i += gridDim.x * blockDim.x)
+        claims[i] = 0;
+    for (uint32_t i = t; i < k; i += gridDim.x * blockDim.x) {
+        done[i].segs_done = 0;
+        done[i].t_done = 0;
+    }
 }
 
-template <int LOG2W, int NT>
+// Number of table primes <= 2^j for j = 0..32 (the planner's bucket bounds).
+__global__ void pow2_counts_kernel(const uint32_t *primes, uint64_t nprimes, uint64_t *out)
+{
+    const uint32_t j = threadIdx.x;
+    if (j <= 32) {
+        const uint64_t x = j == 32 ? 0xFFFFFFFFull : (1ull << j);
+        out[j] = count_le(primes, nprimes, (uint32_t)x);
+    }
+}
+
+template <int LOG2E, int NT>
 hipError_t launch_t(uint32_t grid, const GbProbeArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((sieve_probe_kernel<LOG2W, NT>), dim3(grid), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((sieve_probe_kernel<LOG2E, NT>), dim3(grid), dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 
-template <int LOG2W, int NT>
+template <int LOG2E, int NT>
 hipError_t occ_t(int *n)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, sieve_probe_kernel<LOG2W, NT>, NT, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, sieve_probe_kernel<LOG2E, NT>, NT, 0);
 }
 
 }  // namespace
@@ -359,8 +476,17 @@ hipError_t gb_probe_occupancy(int seg_log2, int wg_size, int *blocks_per_cu)
     GB_DISPATCH(occ_t, blocks_per_cu)
 }
 
-hipError_t gb_launch_reset(GbCounters *ctr, hipStream_t s)
+hipError_t gb_launch_reset(GbCounters *ctr, GbIvDone *done, uint32_t k,
+                           unsigned long long *claims, uint32_t nclaims, hipStream_t s)
 {
-    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, ctr);
+    const uint32_t blocks = k > 256 * 64 ? 64 : (k + 255) / 256 + 1;
+    hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, ctr, done, k, claims, nclaims);
+    return hipGetLastError();
+}
+
+hipError_t gb_launch_pow2_counts(const uint32_t *primes, uint64_t nprimes, uint64_t *out33,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(pow2_counts_kernel, dim3(1), dim3(64), 0, s, primes, nprimes, out33);
     return hipGetLastError();
 }

@@ -38,7 +38,8 @@ def test_library_exports_every_declared_symbol(gb):
 def test_struct_layouts_match_header(gb):
     from paper_2603_07850_amd import _binding as b
     assert ctypes.sizeof(b.Result) == 11 * 8
-    assert ctypes.sizeof(b.Params) == 16
+    assert ctypes.sizeof(b.Params) == 24
+    assert ctypes.sizeof(b.Stats) == 72
 
 
 def test_no_table_is_reported_not_crashed(gb):
@@ -56,14 +57,16 @@ def test_no_table_is_reported_not_crashed(gb):
 def test_host_validation_of_params(gb):
     saved = gb.get_params()
     for bad in (dict(seg_log2=17), dict(seg_log2=21), dict(wg_size=128), dict(wg_size=2048),
-                dict(window=2), dict(window=65537), dict(wg_per_cu=65)):
+                dict(window=2), dict(window=65537), dict(wg_per_cu=65), dict(bucket_log2=16),
+                dict(bucket_log2=33)):
         args = dict(seg_log2=18, wg_size=256, window=4096, wg_per_cu=0)
         args.update(bad)
         with pytest.raises(gb.GoldbachError) as e:
             gb.set_params(**args)
         assert e.value.name == "GB_EINVAL"
-    gb.set_params(seg_log2=20, wg_size=1024, window=0, wg_per_cu=1)
-    assert gb.get_params() == dict(seg_log2=20, wg_size=1024, window=0, wg_per_cu=1)
+    gb.set_params(seg_log2=20, wg_size=1024, window=0, wg_per_cu=1, bucket_log2=24, bucket_mib=512)
+    assert gb.get_params() == dict(seg_log2=20, wg_size=1024, window=0, wg_per_cu=1,
+                                   bucket_log2=24, bucket_mib=512)
     gb.set_params(**saved)
     assert gb.get_params() == saved
 

@@ -41,10 +41,21 @@ def table(gb, limit):
         _current["limit"] = limit
 
 
+_oracle_memo = {}
+
+
+def oracle_range(O, A, B, P_max, limit, cap, seg_evens):
+    key = (A, B, P_max, limit, cap)
+    if key not in _oracle_memo:
+        _oracle_memo[key] = O.verify_range(A, B, P_max, limit, cap=cap, seg_evens=seg_evens)
+    return _oracle_memo[key]
+
+
 def check(gb, O, A, B, P_max, limit, cap=1 << 16, seg_evens=1 << 16):
     table(gb, limit)
+    print("[gpu] verify_range(%d, %d, %d) params=%s" % (A, B, P_max, gb.get_params()), flush=True)
     g = gb.verify_range(A, B, P_max, unresolved_cap=cap)
-    o = O.verify_range(A, B, P_max, limit, cap=cap, seg_evens=seg_evens)
+    o = oracle_range(O, A, B, P_max, limit, cap, seg_evens)
     for f in FIELDS:
         assert g[f] == o[f], (f, A, B, P_max, g[f], o[f])
     return g
@@ -204,3 +215,68 @@ def test_repeat_runs_identical(gb):
     a = gb.verify_range(10**11, 10**11 + 4 * 10**6, 65536)
     for _ in range(3):
         assert gb.verify_range(10**11, 10**11 + 4 * 10**6, 65536) == a
+
+
+def test_batch_graph_replays_identical(gb, O):
+    """The batched form replays a captured graph: every replay, with eager work
+    and synchronizations in between, must equal the first result and the oracle."""
+    import torch
+    table(gb, 10**6)
+    ivs = [(10**9 + 2 * i * 100003, 10**9 + 2 * i * 100003 + 2 * 50000) for i in range(40)]
+    first = gb.verify_batch(ivs, 65536)
+    for (A, B), g in list(zip(ivs, first))[:6]:
+        o = O.verify_range(A, B, 65536, 10**6)
+        for f in FIELDS:
+            assert g[f] == o[f], (f, A, B)
+    for _ in range(4):
+        gb.verify_range(4, 10**6, 65536)          # eager launches between replays
+        torch.cuda.synchronize()
+        assert gb.verify_batch(ivs, 65536) == first
+    lat = gb.last_batch_latencies()
+    assert len(lat) == len(ivs) and all(x > 0 for x in lat)
+    # a different shape re-captures; the old one still replays correctly afterwards
+    other = gb.verify_batch(ivs[:7], 65536)
+    assert other == first[:7]
+    assert gb.verify_batch(ivs, 65536) == first
+
+
+BUCKET_CASES = [
+    # (A, B, P_max, limit)
+    (10**11 + 2 * 4567, 10**11 + 3_000_000, 65536, 10**6),
+    (10**13 - 4 * 10**6, 10**13, 65536, 10**7),
+    (10**15 + 2, 10**15 + 1_500_000, 65536, 2**32 - 1),
+    ((1 << 64) - 2 * 200000, (1 << 64) - 1, 65536, 2**32 - 1),
+    ((1 << 64) - 2 * 6000, (1 << 64) - 3, 7, 2**32 - 1),
+]
+
+
+@pytest.mark.parametrize("blog", [17, 19, 0])
+@pytest.mark.parametrize("mib", [0, 1])
+def test_bucket_lists_parity(gb, O, blog, mib):
+    """Primes above the bucket bound cleared from bucket lists: identical to the
+    oracle, with one or many rounds (a 1 MiB budget splits ranges into many
+    chunks and rounds)."""
+    saved = gb.get_params()
+    try:
+        gb.set_params(seg_log2=18, wg_size=256, window=4096, bucket_log2=blog, bucket_mib=mib)
+        for A, B, P_max, limit in BUCKET_CASES:
+            check(gb, O, A, B, P_max, limit, cap=20000, seg_evens=1 << 22)
+    finally:
+        gb.set_params(**saved)
+
+
+def test_bucket_batch_equals_single(gb, O):
+    table(gb, 2**32 - 1)
+    saved = gb.get_params()
+    try:
+        gb.set_params(seg_log2=19, wg_size=512, window=4096, bucket_log2=18, bucket_mib=64)
+        ivs = [(10**9, 10**9 + 200000), (U64 - 300000, U64), (10**18, 10**18 + 900000),
+               (4, 50000), (2**50 + 2, 2**50 + 2 + 2 * 333333), (10**12, 10**12)]
+        got = gb.verify_batch(ivs, 65536)
+        for (A, B), g in zip(ivs, got):
+            s = gb.verify_range(A, B, 65536)
+            o = O.verify_range(A, B, 65536, 2**32 - 1, seg_evens=1 << 22)
+            for f in FIELDS:
+                assert g[f] == s[f] == o[f], (f, A, B)
+    finally:
+        gb.set_params(**saved)
