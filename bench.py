@@ -16,7 +16,9 @@ Extra legs (also in the JSON line):
   cpu_baseline  the CPU oracle, timed on this host's cores over a bounded
                 sample of seeded 10^7-wide windows of the same range;
   batched       (--batched) 4096 seeded uneven intervals in one persistent
-                launch vs one launch per interval, with p50/p99 latency.
+                launch vs one launch per interval, with p50/p99 latency;
+  served        (--served) the seeded Poisson request trace through the
+                continuous-batching server at 0.7x the batched capacity.
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
        python bench.py --copy-calibration     (plain 1 GiB copies, for counters)
@@ -42,6 +44,10 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 OPS_PER_WORD_OP = 4.0
 
 
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def evens_in(A, B):
     a = max(4, A + (A & 1))
     b = B - (B & 1)
@@ -57,13 +63,13 @@ def algorithmic_ops_per_even(wm, seg_log2, halo_bits):
     """Strikes and word-tests per even of the headline range, priced in lane-ops.
 
     strikes per odd (primes 37..sqrt(q), Mertens sum over the real table), one
-    presieve word write per 32 odds, all scaled by the halo factor W/(W-H)
+    presieve word write per 32 odds, all scaled by the halo factor (E+H)/E
     (window bits per even); word-tests per even = mean max rank of a 32-even
     block / 32 (the word-parallel probe tests a block against every candidate
     up to its largest p_min)."""
     h = wm["headline"]
-    W = 1 << seg_log2
-    halo = W / (W - halo_bits)
+    E = 1 << seg_log2            # evens per segment; the window holds E + H bits
+    halo = (E + halo_bits) / E
     strikes = (h["strikes_per_odd"] + 1.0 / 32) * halo
     tests = h["mean_block_max_rank"] / 32.0
     return OPS_PER_WORD_OP * (strikes + tests)
@@ -104,11 +110,14 @@ def run_batched(gb, steps):
         res = gb.verify_batch(ivs, 65536)
     dt = (time.perf_counter() - t0) / steps
     lat = gb.last_batch_latencies()
+    log("batched: %d intervals in %.3f s per launch; per-interval baseline next" % (len(ivs), dt))
     t0 = time.perf_counter()
     done = []
-    for a, b in ivs:
+    for i, (a, b) in enumerate(ivs):
         gb.verify_range(a, b, 65536)
         done.append(time.perf_counter() - t0)
+        if i % 256 == 255:
+            log("per-interval: %d / %d after %.1f s" % (i + 1, len(ivs), done[-1]))
     dt1 = done[-1]
     q = lambda xs, p: sorted(xs)[min(len(xs) - 1, int(p * len(xs)))]
     return {
@@ -120,6 +129,48 @@ def run_batched(gb, steps):
         "all_verified": all(r["n_failed"] == 0 for r in res),
         "median_batched_latency_ms": statistics.median(lat) * 1e3,
     }
+
+
+def run_served(gb, capacity_evens_per_s, load=0.7, n_requests=2000, seed=3001):
+    """Poisson arrivals of the seeded request trace at `load` x the measured
+    batched capacity; every request verified by the continuous-batching server."""
+    import threading
+
+    from paper_2603_07850_amd import workloads as Wl
+    # offered load in evens/s -> arrival rate for the trace's mean request size
+    probe = Wl.request_trace(seed=seed, n=n_requests, rate_per_s=1.0)
+    mean_evens = sum((b - a) // 2 + 1 for _, a, b in probe) / len(probe)
+    rate = load * capacity_evens_per_s / mean_evens
+    trace = Wl.request_trace(seed=seed, n=n_requests, rate_per_s=rate)
+    gb.base_primes(2**32 - 1)
+    lat, done = [], []
+    total_evens = sum((b - a) // 2 + 1 for _, a, b in trace)
+    with gb.Server(65536, hbm_budget_bytes=64 << 30, max_active=64, piece_segments=256) as srv:
+        def consumer():
+            while len(done) < len(trace):
+                r = srv.poll(wait_ms=1000)
+                if r is not None:
+                    lat.append(r[2])
+                    done.append(r[1]["n_failed"] == 0)
+                    if len(done) % 250 == 0:
+                        log("served: %d / %d requests done" % (len(done), len(trace)))
+        th = threading.Thread(target=consumer)
+        th.start()
+        t0 = time.perf_counter()
+        for t, a, b in trace:
+            dt = t - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            srv.submit(a, b)
+        th.join()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    q = lambda xs, p: sorted(xs)[min(len(xs) - 1, int(p * len(xs)))]
+    return {"requests": len(trace), "offered_load": load, "arrival_rate_per_s": rate,
+            "evens": total_evens, "evens_per_s": total_evens / wall, "wall_s": wall,
+            "p50_ms": q(lat, 0.5) * 1e3, "p99_ms": q(lat, 0.99) * 1e3,
+            "ticks": st["ticks"], "busy_frac": st["busy_ms"] / (wall * 1e3),
+            "all_verified": all(done)}
 
 
 def copy_calibration():
@@ -142,6 +193,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-windows", type=int, default=96)
     ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--served", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -175,6 +227,7 @@ def main():
         gb.base_primes(limit)
         return gb.verify_range(A, B, P_max)
 
+    log("headline: params %s; %d warmup + %d timed steps" % (params, args.warmup, args.steps))
     for _ in range(args.warmup):
         ref = step()
     torch.cuda.synchronize()
@@ -214,8 +267,10 @@ def main():
         "results_consistent": ok,
         "roofline": roofline,
     }
-    if args.batched:
+    if args.batched or args.served:
         out["batched"] = run_batched(gb, 2)
+    if args.served:
+        out["served"] = run_served(gb, out["batched"]["batched_evens_per_s"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_windows)
     print(json.dumps(out), flush=True)

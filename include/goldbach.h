@@ -94,10 +94,10 @@ typedef struct gb_result {
  *   wg_per_cu  workgroups per compute unit in the persistent grid; 0 = the
  *              maximum that LDS allows.
  *   bucket_log2  primes above 2^bucket_log2 are not sieved segment by segment
- *              but through per-segment bucket lists filled once per run of
- *              segments; 0 = seg_log2 + 1, else 17..32 (32 = never).
- *   bucket_mib HBM budget for the bucket lists of one round, in MiB
- *              (0 = 4096); larger batches run in several rounds.
+ *              but through per-segment strike bitmaps in HBM, filled once per
+ *              run of segments; 0 = seg_log2 + 1, else 17..32 (32 = never).
+ *   bucket_mib HBM budget for the strike bitmaps of one round, in MiB
+ *              (0 = 512); larger batches run in several rounds.
  */
 typedef struct gb_params {
     uint32_t seg_log2;
@@ -162,9 +162,11 @@ gb_status gb_set_params(const gb_params *p);
 gb_status gb_get_params(gb_params *p);
 
 /*
- * Time a calibration run of [A, B] (at most 2^36 evens) under each supported
- * parameter set, keep the fastest as the current parameters and write it to
- * *best (may be NULL).  Results of later calls do not depend on the choice.
+ * Autotuner: time a calibration run of [A, B] (at most 2^36 evens) under each
+ * segment size, workgroup size and probe window (and, when isqrt(B) > 2^19,
+ * with and without bucket lists), keep the fastest as the current parameters
+ * and write it to *best (may be NULL).  Results of later calls do not depend
+ * on the choice.
  */
 gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream,
                       gb_params *best);
@@ -226,8 +228,8 @@ gb_status gb_last_latencies(double *ms, uint64_t k);
  * rebuilt or released while a server is open.
  *
  *   hbm_budget_bytes  admission budget: the sum of the active requests'
- *                     reservations (bucket lists and records of one piece,
- *                     estimated from the range's top) stays within it; a
+ *                     reservations (strike bitmaps and records of one piece)
+ *                     stays within it; a
  *                     request whose reservation alone exceeds it is refused
  *                     with GB_ENOMEM at submission.
  *   P_max             candidate bound for every request (as gb_verify_range).

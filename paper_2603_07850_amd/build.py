@@ -20,6 +20,10 @@ FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
     # packed fp32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no three-input bitwise ops: this compiler's fusion of AND/XOR chains into
+    # v_bitop3 produced wrong masks in the probe loop (checked lane by lane
+    # against numpy on an MI355X); plain v_and/v_xor are used instead
+    "-Xclang", "-target-feature", "-Xclang", "-bitop3-insts",
     "-I" + os.path.join(ROOT, "include"),
     "-Wall", "-Wno-unused-function",
 ]

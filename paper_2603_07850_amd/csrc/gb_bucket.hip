@@ -1,4 +1,4 @@
-// gb_bucket.hip -- bucket lists for the primes above the bucket bound.
+// gb_bucket.hip -- strike bitmaps for the primes above the bucket bound.
 //
 // A prime p much larger than a segment window strikes a window at most once,
 // so computing its first multiple in every segment (one 64-by-32-bit
@@ -6,14 +6,16 @@
 // themselves; near 2^64 there are 2*10^8 such primes per segment.  Here the
 // remainder is taken once per chunk (a run of consecutive segments of one
 // interval) and prime, the prime's multiples are walked across the chunk, and
-// each strike is appended, as a window bit offset, to the bucket of the
-// segment that owns it -- and of the previous segment too when it falls in
-// the halo the two windows share.  The segment kernel then clears its
-// bucket's bits in LDS.
+// each strike sets its window bit in the strike bitmap of the segment that
+// owns it -- and of the previous segment too when it falls in the halo the
+// two windows share -- with one non-returning atomic OR.  Strikes of one
+// segment land on words spread over its window, so they do not queue on one
+// address.  The segment kernel folds its bitmap into the LDS window.
 //
 // Work is cut into items (prime, sub-range of the chunk): primes of the band
 // (2^b, 2^(b+1)] get sub-ranges of 8 * 2^b bits, so an item takes one
-// remainder and makes at most 16 strikes whatever the prime's size.  Every
+// remainder and makes at most 16 strikes whatever the prime's size.  A tile
+// is one sub-range against kFillThreads * kFillPerThread consecutive primes.  Every
 // offset is relative to the chunk's window start and bounded by the chunk's
 // last odd number, so no absolute value beyond it is formed (the overflow
 // guards of the paper's Sec. 3.4).
@@ -22,19 +24,14 @@
 
 namespace {
 
-__device__ __forceinline__ void append(const GbBucketArgs &a, uint64_t g, uint32_t off)
+__device__ __forceinline__ void strike(const GbBucketArgs &a, uint64_t g, uint32_t off)
 {
     const uint64_t rel = g - a.seg_base;
-    const uint32_t idx = atomicAdd(&a.bcount[rel], 1u);
-    if (idx < a.bcap)
-        a.bucket[rel * a.bcap + idx] = off;
+    atomicOr(&a.bitmap[rel * a.words + (off >> 5)], 1u << (off & 31));
 }
 
-__global__ __launch_bounds__(kFillThreads) void bucket_fill_kernel(GbBucketArgs a)
+__device__ void fill_tile(const GbBucketArgs &a, uint64_t tile)
 {
-    const uint64_t tile = blockIdx.x;
-    if (tile >= a.ntiles)
-        return;
     uint32_t lo = 0, hi = a.ntask - 1;   // last task whose first tile <= tile
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) >> 1;
@@ -47,26 +44,28 @@ __global__ __launch_bounds__(kFillThreads) void bucket_fill_kernel(GbBucketArgs 
     const GbChunk C = a.chunk[T.chunk];
     const uint32_t E = 1u << a.log2e;
     const uint32_t emask = E - 1;
-    const uint64_t items = (uint64_t)T.np * T.nsub;
-    const uint64_t base = (tile - T.tile_first) * (uint64_t)(kFillThreads * kFillPerThread);
+    // tile -> (sub-range j, block of kFillThreads * kFillPerThread primes)
+    constexpr uint32_t PB = kFillThreads * kFillPerThread;
+    const uint32_t pblocks = (T.np + PB - 1) / PB;
+    const uint64_t t = tile - T.tile_first;
+    const uint32_t j = (uint32_t)(t / pblocks);
+    const uint32_t pb = (uint32_t)(t - (uint64_t)j * pblocks);
+    const uint64_t b0 = (uint64_t)j << T.sl_log2;        // first bit of the sub-range
+    if (b0 > C.dmax)
+        return;
+    uint64_t b1 = b0 + (1ull << T.sl_log2) - 1;          // last bit of the sub-range
+    if (b1 > C.dmax)
+        b1 = C.dmax;
+    const uint64_t qs = C.Q0 + 2 * b0;                   // <= the chunk's last odd number
     for (uint32_t m = 0; m < kFillPerThread; ++m) {
-        const uint64_t w = base + threadIdx.x + (uint64_t)m * kFillThreads;
-        if (w >= items)
+        const uint32_t pi = pb * PB + threadIdx.x + m * kFillThreads;
+        if (pi >= T.np)
             break;
-        const uint32_t pi = (uint32_t)(w % T.np);
-        const uint32_t j = (uint32_t)(w / T.np);
         const uint64_t idx = (uint64_t)T.p_first + pi;
         if (idx >= C.p_root)
-            continue;
+            break;
         const uint32_t p = a.primes[idx];
-        const uint64_t b0 = (uint64_t)j << T.sl_log2;        // first bit of the sub-range
-        if (b0 > C.dmax)
-            continue;
-        uint64_t b1 = b0 + (1ull << T.sl_log2) - 1;          // last bit of the sub-range
-        if (b1 > C.dmax)
-            b1 = C.dmax;
         // first odd multiple of p at or above max(Q0 + 2*b0, p^2), as a window bit
-        const uint64_t qs = C.Q0 + 2 * b0;                   // <= the chunk's last odd number
         const uint32_t r = gb_mod_u64_u32(qs, p);
         uint64_t x = r ? p - r : 0;
         if (x & 1)
@@ -82,18 +81,26 @@ __global__ __launch_bounds__(kFillThreads) void bucket_fill_kernel(GbBucketArgs 
             const uint64_t s = d >> a.log2e;
             const uint32_t off = (uint32_t)d & emask;
             if (s < C.nseg)
-                append(a, C.seg_first + s, off);
+                strike(a, C.seg_first + s, off);
             if (off < a.H && s >= 1 && s - 1 < C.nseg)
-                append(a, C.seg_first + s - 1, off + E);
+                strike(a, C.seg_first + s - 1, off + E);
         }
     }
 }
 
-__global__ void bucket_reset_kernel(uint32_t *bcount, uint64_t nsegs)
+// Grid-stride over the round's tiles (the grid is capped well below the
+// 2^32 work-item limit of one launch).
+__global__ __launch_bounds__(kFillThreads) void bucket_fill_kernel(GbBucketArgs a)
+{
+    for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x)
+        fill_tile(a, tile);
+}
+
+__global__ void bucket_reset_kernel(uint32_t *bitmap, uint64_t words)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsegs; i += stride)
-        bcount[i] = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+        bitmap[i] = 0;
 }
 
 // p_root of each chunk: the number of table primes <= isqrt(its top).
@@ -117,15 +124,14 @@ __global__ void chunk_roots_kernel(const uint32_t *primes, uint64_t nprimes, GbC
 
 }  // namespace
 
-hipError_t gb_launch_bucket_reset(uint32_t *bcount, uint64_t nsegs, unsigned long long *,
-                                  hipStream_t s)
+hipError_t gb_launch_bucket_reset(uint32_t *bitmap, uint64_t words, hipStream_t s)
 {
-    uint64_t blocks = (nsegs + 255) / 256;
+    uint64_t blocks = (words + 255) / 256;
     if (blocks < 1)
         blocks = 1;
-    if (blocks > 4096)
-        blocks = 4096;
-    hipLaunchKernelGGL(bucket_reset_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, bcount, nsegs);
+    if (blocks > 16384)
+        blocks = 16384;
+    hipLaunchKernelGGL(bucket_reset_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, bitmap, words);
     return hipGetLastError();
 }
 

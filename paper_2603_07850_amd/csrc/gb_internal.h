@@ -75,11 +75,8 @@ struct GbProbeArgs {
     GbCounters *ctr;
     unsigned long long *claim;  // this launch's segment queue head
     GbIvDone *done;
-    const uint32_t *bucket;   // per segment: bcap window bits struck by large primes
-    const uint32_t *bcount;   // per segment: entries appended (may exceed bcap)
-    uint32_t bcap;            // 0 when the launch has no buckets
-    uint32_t pad;
-    unsigned long long *bover;  // largest bucket count seen above bcap (overflow report)
+    const uint32_t *bitmap;   // per segment (E + H)/32 words: bits struck by large
+                              // primes; null when the launch has no buckets
 };
 
 // A run of consecutive segments of one interval that the bucket-fill kernel
@@ -112,11 +109,10 @@ struct GbBucketArgs {
     uint32_t ntask;
     uint32_t log2e;
     uint32_t H;
-    uint32_t bcap;
+    uint32_t words;       // bitmap words per segment, (E + H)/32
     uint64_t ntiles;
     uint64_t seg_base;    // global index of the round's first segment
-    uint32_t *bucket;
-    uint32_t *bcount;
+    uint32_t *bitmap;     // the round's strike bitmaps, segment after segment
 };
 
 // Set the calling thread's gb_last_error() message (host code).
@@ -146,8 +142,7 @@ hipError_t gb_probe_occupancy(int seg_log2, int wg_size, int *blocks_per_cu);
 constexpr uint32_t kFillThreads = 256;
 constexpr uint32_t kFillPerThread = 4;   // work items per thread in one fill tile
 constexpr uint32_t kFillStrikes = 8;     // sub-range = kFillStrikes * 2^b bits for band b
-hipError_t gb_launch_bucket_reset(uint32_t *bcount, uint64_t nsegs, unsigned long long *bover,
-                                  hipStream_t s);
+hipError_t gb_launch_bucket_reset(uint32_t *bitmap, uint64_t words, hipStream_t s);
 hipError_t gb_launch_bucket_fill(const GbBucketArgs &a, uint32_t grid, hipStream_t s);
 
 hipError_t gb_launch_phase2(const uint32_t *primes, uint64_t nprimes, uint64_t first_idx,

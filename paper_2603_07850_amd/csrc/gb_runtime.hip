@@ -135,9 +135,9 @@ struct Ctx {
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uint64_t> graph_key;    // every value the captured sequence bakes in
     // bucket lists of the large primes
-    DevBuf d_bucket, d_bcount, d_chunk, d_claims, d_task;
+    DevBuf d_bitmap, d_chunk, d_claims, d_task;
     HostBuf h_chunk, h_task;
-    double bcap_scale = 1.0;            // grows when a bucket overflowed
+    std::vector<uint64_t> last_slot;    // last call: caller's index -> kernel slot
 };
 
 Ctx &ctx()
@@ -212,8 +212,7 @@ void release_all(Ctx &c)
     c.d_ctr.release();
     c.d_done.release();
     c.h_done.release();
-    c.d_bucket.release();
-    c.d_bcount.release();
+    c.d_bitmap.release();
     c.d_chunk.release();
     c.d_claims.release();
     c.d_task.release();
@@ -337,7 +336,7 @@ uint64_t small_count_le(const Ctx &c, uint64_t x)
 struct Round {
     uint64_t seg_base = 0;    // global index of the round's first segment
     uint64_t nsegs = 0;
-    uint32_t bcap = 0;        // bucket entries per segment (0: no buckets)
+    uint32_t bm = 0;          // 1: primes above the bucket bound go through strike bitmaps
     uint64_t chunk_first = 0; // chunks of this round in Plan::chunks
     uint64_t nchunk = 0;
     uint64_t task_first = 0;  // fill tasks of this round in Plan::tasks
@@ -352,13 +351,16 @@ struct Plan {
     uint64_t lb = 0;          // bucket bound: larger primes go through buckets
     uint64_t total_segs = 0;
     uint64_t total_evens = 0;
-    std::vector<GbInterval> iv;
+    std::vector<GbInterval> iv;       // in the caller's order
+    std::vector<GbInterval> dev_iv;   // in segment order (what the kernels see)
+    std::vector<uint64_t> slot;       // caller's index -> position in dev_iv
     std::vector<uint64_t> An, Bn;
     std::vector<Round> rounds;
     std::vector<GbChunk> chunks;
     std::vector<GbFillTask> tasks;
     uint64_t max_round_segs = 0;
-    uint64_t max_bucket_words = 0;
+    uint64_t max_bitmap_words = 0;
+    uint32_t words = 0;       // window words per segment, (E + H)/32
 };
 
 // pi(x) < 1.25506 x / ln x for x > 1 (Rosser and Schoenfeld 1962).
@@ -400,12 +402,13 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
         blog = 32;
     pl.lb = blog >= 32 ? 0xFFFFFFFFull : (1ull << blog);
     pl.lb_count = (uint32_t)std::min<uint64_t>(blog >= 32 ? c.nprimes : c.pi2[blog], c.nprimes);
-    const uint64_t budget = (uint64_t)(pr.bucket_mib ? pr.bucket_mib : 4096) << 20;
+    const uint64_t budget = (uint64_t)(pr.bucket_mib ? pr.bucket_mib : 512) << 20;
+    pl.words = (uint32_t)(Wbits / 32);
 
     pl.iv.resize(k);
     pl.An.resize(k);
     pl.Bn.resize(k);
-    std::vector<double> hits(k, 0.0);   // expected bucket strikes per segment
+    std::vector<double> hits(k, 0.0);   // > 0: the interval needs primes above the bound
     std::vector<uint64_t> order;
     order.reserve(k);
     uint64_t evens = 0;
@@ -434,8 +437,7 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
         order.push_back(i);
     }
     // segments are numbered interval by interval; intervals without bucket
-    // work come first, then by growing expected strikes per segment, so that
-    // one round groups segments of similar bucket capacity
+    // work come first, then the others by growing top
     std::stable_sort(order.begin(), order.end(),
                      [&](uint64_t x, uint64_t y) { return hits[x] < hits[y]; });
     uint64_t seg = 0;
@@ -467,7 +469,7 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
         if (cur.nsegs) {
             pl.rounds.push_back(cur);
             pl.max_round_segs = std::max(pl.max_round_segs, cur.nsegs);
-            pl.max_bucket_words = std::max(pl.max_bucket_words, cur.nsegs * (uint64_t)cur.bcap);
+            pl.max_bitmap_words = std::max(pl.max_bitmap_words, cur.nsegs * (uint64_t)pl.words);
         }
         cur = Round();
         cur.seg_base = pos;
@@ -480,17 +482,10 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
     for (; oi < order.size(); ++oi) {
         const uint64_t i = order[oi];
         const GbInterval &I = pl.iv[i];
-        const double h = hits[i] * c.bcap_scale;
-        uint64_t bcap = (uint64_t)(1.1 * h + 6.0 * std::sqrt(h) + 1024.0);
-        bcap = (bcap + 63) & ~63ull;
-        if (bcap > 0xFFFFFFF0ull) {
-            set_err("bucket capacity per segment out of range");
-            return GB_ENOMEM;
-        }
-        // chunk length: every chunk fits a round on its own within the budget
-        uint64_t cmax = budget / (bcap * 4);
+        // chunk length: a chunk's strike bitmaps fit one round within the budget
+        uint64_t cmax = budget / ((uint64_t)pl.words * 4);
         if (cmax < 1) {
-            set_err("bucket budget of %llu MiB is below one segment's bucket",
+            set_err("bucket budget of %llu MiB is below one segment's strike bitmap",
                     (unsigned long long)(budget >> 20));
             return GB_ENOMEM;
         }
@@ -523,18 +518,14 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
                 t.sl_log2 = bb + 3;   // kFillStrikes * 2^b bits
                 t.nsub = (uint32_t)(((ch.dmax + 1) + (1ull << t.sl_log2) - 1) >> t.sl_log2);
                 t.tile_first = tiles;
-                tiles += ((uint64_t)t.np * t.nsub + per_tile - 1) / per_tile;
+                tiles += (uint64_t)t.nsub * ((t.np + per_tile - 1) / per_tile);
                 ts.push_back(t);
             }
-            if (tiles > (1ull << 30)) {
-                set_err("bucket fill of one chunk needs %llu tiles", (unsigned long long)tiles);
-                return GB_ENOMEM;
-            }
-            const uint32_t ncap = (uint32_t)std::max<uint64_t>(cur.bcap, bcap);
-            if (cur.nsegs && ((cur.nsegs + ns) * (uint64_t)ncap * 4 > budget ||
-                              cur.ntiles + tiles > (1ull << 30)))
+
+            if (cur.nsegs && ((cur.nsegs + ns) * (uint64_t)pl.words * 4 > budget ||
+                              cur.ntiles + tiles > (1ull << 40)))
                 close_round();
-            cur.bcap = (uint32_t)std::max<uint64_t>(cur.bcap, bcap);
+            cur.bm = 1;
             ch.seg_first = I.seg_first + s0;
             const uint32_t cidx = (uint32_t)(pl.chunks.size() - cur.chunk_first);
             for (GbFillTask &t : ts) {
@@ -553,6 +544,14 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
     close_round();
     for (const Round &r : pl.rounds)
         pl.max_round_segs = std::max(pl.max_round_segs, r.nsegs);
+    // the kernels locate a segment's interval by binary search over seg_first,
+    // so they see the intervals in segment order
+    pl.dev_iv.resize(k);
+    pl.slot.resize(k);
+    for (uint64_t j = 0; j < k; ++j) {
+        pl.dev_iv[j] = pl.iv[order[j]];
+        pl.slot[order[j]] = j;
+    }
     return GB_OK;
 }
 
@@ -575,8 +574,8 @@ gb_status enqueue_kernels(Ctx &c, const Plan &pl, uint64_t P_max, const gb_param
         GB_HIP(hipEventRecord(c.ev[1], s));
     for (size_t ri = 0; ri < pl.rounds.size(); ++ri) {
         const Round &r = pl.rounds[ri];
-        if (r.bcap) {
-            GB_HIP(gb_launch_bucket_reset((uint32_t *)c.d_bcount.p, r.nsegs, nullptr, s));
+        if (r.bm) {
+            GB_HIP(gb_launch_bucket_reset((uint32_t *)c.d_bitmap.p, r.nsegs * (uint64_t)pl.words, s));
             GbBucketArgs b = {};
             b.primes = (const uint32_t *)c.primes.p;
             b.chunk = (const GbChunk *)c.d_chunk.p + r.chunk_first;
@@ -584,13 +583,12 @@ gb_status enqueue_kernels(Ctx &c, const Plan &pl, uint64_t P_max, const gb_param
             b.ntask = (uint32_t)r.ntask;
             b.log2e = pr.seg_log2;
             b.H = pl.H;
-            b.bcap = r.bcap;
+            b.words = pl.words;
             b.ntiles = r.ntiles;
             b.seg_base = r.seg_base;
-            b.bucket = (uint32_t *)c.d_bucket.p;
-            b.bcount = (uint32_t *)c.d_bcount.p;
+            b.bitmap = (uint32_t *)c.d_bitmap.p;
             if (r.ntask && r.ntiles)
-                GB_HIP(gb_launch_bucket_fill(b, (uint32_t)r.ntiles, s));
+                GB_HIP(gb_launch_bucket_fill(b, (uint32_t)std::min<uint64_t>(r.ntiles, 1u << 16), s));
         }
         GbProbeArgs a = {};
         a.primes = (const uint32_t *)c.primes.p;
@@ -599,7 +597,7 @@ gb_status enqueue_kernels(Ctx &c, const Plan &pl, uint64_t P_max, const gb_param
         a.k = (uint32_t)k;
         a.H = pl.H;
         a.ncand = pl.ncand;
-        a.lb_count = r.bcap ? pl.lb_count : (uint32_t)c.nprimes;
+        a.lb_count = r.bm ? pl.lb_count : (uint32_t)c.nprimes;
         a.seg_base = r.seg_base;
         a.nsegs = r.nsegs;
         a.rec = (GbSegRecord *)c.d_rec.p;
@@ -608,10 +606,7 @@ gb_status enqueue_kernels(Ctx &c, const Plan &pl, uint64_t P_max, const gb_param
         a.ctr = ctr;
         a.claim = claims + ri;
         a.done = (GbIvDone *)c.d_done.p;
-        a.bucket = (const uint32_t *)c.d_bucket.p;
-        a.bcount = (const uint32_t *)c.d_bcount.p;
-        a.bcap = r.bcap;
-        a.bover = (unsigned long long *)&ctr->pad[0];
+        a.bitmap = r.bm ? (const uint32_t *)c.d_bitmap.p : nullptr;
         const uint32_t g = (uint32_t)std::min<uint64_t>(grid, r.nsegs);
         GB_HIP(gb_launch_probe((int)pr.seg_log2, (int)pr.wg_size, g, a, s));
     }
@@ -642,14 +637,14 @@ std::vector<uint64_t> graph_key(const Ctx &c, const Plan &pl, uint64_t P_max, co
     std::vector<uint64_t> key = {
         (uint64_t)c.primes.p, (uint64_t)c.d_iv.p, (uint64_t)c.d_rec.p, (uint64_t)c.d_spill.p,
         (uint64_t)c.d_unres.p, (uint64_t)c.d_res.p, (uint64_t)c.d_ctr.p, (uint64_t)c.d_done.p,
-        (uint64_t)c.d_bucket.p, (uint64_t)c.d_bcount.p, (uint64_t)c.d_chunk.p,
+        (uint64_t)c.d_bitmap.p, (uint64_t)pl.words, (uint64_t)c.d_chunk.p,
         (uint64_t)c.d_claims.p, (uint64_t)c.d_task.p, pl.chunks.size(), c.nprimes, pl.iv.size(),
         c.spill_cap, P_max, pl.H, pl.ncand,
         pl.lb_count, pr.seg_log2, pr.wg_size, grid, (uint64_t)c.num_cu};
     for (const Round &r : pl.rounds) {
         key.push_back(r.seg_base);
         key.push_back(r.nsegs);
-        key.push_back(r.bcap);
+        key.push_back(r.bm);
         key.push_back(r.chunk_first);
         key.push_back(r.nchunk);
         key.push_back(r.task_first);
@@ -696,7 +691,7 @@ gb_status capture_graph(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params 
 // One pass of the launch sequence; the caller retries when a capacity
 // (spill list, bucket) overflowed.
 gb_status run_once(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr, hipStream_t s,
-                   bool use_graph, uint64_t *spills_out, uint64_t *bover_out)
+                   bool use_graph, uint64_t *spills_out)
 {
     const uint64_t k = pl.iv.size();
     const uint64_t nr = std::max<size_t>(pl.rounds.size(), 1);
@@ -710,8 +705,7 @@ gb_status run_once(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr, 
     GB_TRY(c.h_chunk.reserve(std::max<size_t>(pl.chunks.size(), 1) * sizeof(GbChunk)));
     GB_TRY(c.d_task.reserve(std::max<size_t>(pl.tasks.size(), 1) * sizeof(GbFillTask)));
     GB_TRY(c.h_task.reserve(std::max<size_t>(pl.tasks.size(), 1) * sizeof(GbFillTask)));
-    GB_TRY(c.d_bcount.reserve(std::max<uint64_t>(pl.max_round_segs, 1) * 4));
-    GB_TRY(c.d_bucket.reserve(std::max<uint64_t>(pl.max_bucket_words, 1) * 4));
+    GB_TRY(c.d_bitmap.reserve(std::max<uint64_t>(pl.max_bitmap_words, 1) * 4));
     GB_TRY(c.h_iv.reserve(k * sizeof(GbInterval)));
     GB_TRY(c.h_res.reserve(k * sizeof(GbIvResult)));
     GB_TRY(c.h_ctr.reserve(sizeof(GbCounters)));
@@ -732,7 +726,7 @@ gb_status run_once(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr, 
             occ = std::min<int>(occ, (int)pr.wg_per_cu);
         grid = (uint32_t)std::min<uint64_t>(pl.total_segs, (uint64_t)c.num_cu * occ);
     }
-    std::memcpy(c.h_iv.p, pl.iv.data(), k * sizeof(GbInterval));
+    std::memcpy(c.h_iv.p, pl.dev_iv.data(), k * sizeof(GbInterval));
     GB_HIP(hipMemcpyAsync(c.d_iv.p, c.h_iv.p, k * sizeof(GbInterval), hipMemcpyHostToDevice, s));
     if (!pl.chunks.empty()) {
         std::memcpy(c.h_chunk.p, pl.chunks.data(), pl.chunks.size() * sizeof(GbChunk));
@@ -759,7 +753,6 @@ gb_status run_once(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr, 
     GB_HIP(hipStreamSynchronize(s));
     const GbCounters *hc = (const GbCounters *)c.h_ctr.p;
     *spills_out = hc->spills;
-    *bover_out = hc->pad[0];
     float total = 0;
     GB_HIP(hipEventElapsedTime(&total, c.ev[0], c.ev[3]));
     const GbIvDone *hd = (const GbIvDone *)c.h_done.p;
@@ -807,28 +800,24 @@ gb_status verify_many(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, hi
     if (c.spill_cap == 0)
         c.spill_cap = 1 << 16;
     Plan pl;
-    uint64_t spills = 0, bover = 0;
+    uint64_t spills = 0;
+    GB_TRY(make_plan(c, AB, k, P_max, pr, pl));
     for (int attempt = 0;; ++attempt) {
-        pl = Plan();
-        GB_TRY(make_plan(c, AB, k, P_max, pr, pl));
-        GB_TRY(run_once(c, pl, P_max, pr, s, use_graph, &spills, &bover));
-        if (spills <= c.spill_cap && bover == 0)
+        GB_TRY(run_once(c, pl, P_max, pr, s, use_graph, &spills));
+        if (spills <= c.spill_cap)
             break;
-        if (attempt >= 4) {
-            set_err("capacities kept overflowing (spills %llu, bucket %llu)",
-                    (unsigned long long)spills, (unsigned long long)bover);
+        if (attempt >= 3) {
+            set_err("spill list kept overflowing (%llu entries)", (unsigned long long)spills);
             return GB_ENOMEM;
         }
-        if (spills > c.spill_cap)
-            c.spill_cap = spills + spills / 4 + 1024;
-        if (bover)
-            c.bcap_scale *= 2.0;   // a bucket overflowed: rerun with larger buckets
+        c.spill_cap = spills + spills / 4 + 1024;   // rerun with room for every spill
     }
     const GbIvResult *res = (const GbIvResult *)c.h_res.p;
+    c.last_slot = pl.slot;
     gb_status status = GB_OK;
     for (uint64_t i = 0; i < k; ++i) {
         gb_result &o = outs[i];
-        const GbIvResult &r = res[i];
+        const GbIvResult &r = res[pl.slot[i]];
         o.A = pl.An[i];
         o.B = pl.Bn[i];
         o.P_max = P_max;
@@ -965,37 +954,42 @@ gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream, gb_p
     const uint32_t logs[3] = {18, 19, 20};
     const uint32_t wgs[3] = {256, 512, 1024};
     const uint32_t wins[2] = {4096, 16384};
+    // the bucket bound matters only when the range reaches primes above 2^19
+    const bool big = isqrt_u64(Bn) > (1ull << 19);
+    const uint32_t blogs[2] = {0, 32};
+    const int nb = big ? 2 : 1;
     double best_t = 1e300;
     gb_params best_p = saved;
     const uint64_t AB[2] = {A, B};
     hipStream_t s = (hipStream_t)stream;
     for (uint32_t lg : logs)
         for (uint32_t wg : wgs)
-            for (uint32_t win : wins) {
-                gb_params p = {lg, wg, win, 0, saved.bucket_log2, saved.bucket_mib};
-                int occ = 0;
-                if (gb_probe_occupancy((int)lg, (int)wg, &occ) != hipSuccess || occ < 1) {
-                    (void)hipGetLastError();
-                    continue;
-                }
-                c.params = p;
-                gb_result r = {};
-                double tmin = 1e300;
-                for (int rep = 0; rep < 2; ++rep) {
-                    const auto t0 = std::chrono::steady_clock::now();
-                    gb_status st = verify_many(c, AB, 1, P_max, s, &r, false);
-                    const auto t1 = std::chrono::steady_clock::now();
-                    if (st != GB_OK && st != GB_ETRUNC) {
-                        c.params = saved;
-                        return st;
+            for (uint32_t win : wins)
+                for (int bi = 0; bi < nb; ++bi) {
+                    gb_params p = {lg, wg, win, 0, big ? blogs[bi] : saved.bucket_log2, saved.bucket_mib};
+                    int occ = 0;
+                    if (gb_probe_occupancy((int)lg, (int)wg, &occ) != hipSuccess || occ < 1) {
+                        (void)hipGetLastError();
+                        continue;
                     }
-                    tmin = std::min(tmin, std::chrono::duration<double>(t1 - t0).count());
+                    c.params = p;
+                    gb_result r = {};
+                    double tmin = 1e300;
+                    for (int rep = 0; rep < 2; ++rep) {
+                        const auto t0 = std::chrono::steady_clock::now();
+                        gb_status st = verify_many(c, AB, 1, P_max, s, &r, false);
+                        const auto t1 = std::chrono::steady_clock::now();
+                        if (st != GB_OK && st != GB_ETRUNC) {
+                            c.params = saved;
+                            return st;
+                        }
+                        tmin = std::min(tmin, std::chrono::duration<double>(t1 - t0).count());
+                    }
+                    if (tmin < best_t) {
+                        best_t = tmin;
+                        best_p = p;
+                    }
                 }
-                if (tmin < best_t) {
-                    best_t = tmin;
-                    best_p = p;
-                }
-            }
     c.params = best_p;
     if (best)
         *best = best_p;
@@ -1053,8 +1047,10 @@ gb_status gb_last_latencies(double *ms, uint64_t k)
         return GB_EINVAL;
     }
     const GbIvDone *hd = (const GbIvDone *)c.h_done.p;
-    for (uint64_t i = 0; i < k; ++i)
-        ms[i] = hd[i].t_done ? (double)(hd[i].t_done - c.last_t_start) / c.wall_khz : 0.0;
+    for (uint64_t i = 0; i < k; ++i) {
+        const uint64_t j = i < c.last_slot.size() ? c.last_slot[i] : i;
+        ms[i] = hd[j].t_done ? (double)(hd[j].t_done - c.last_t_start) / c.wall_khz : 0.0;
+    }
     return GB_OK;
 }
 

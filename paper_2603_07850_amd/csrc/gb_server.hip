@@ -93,19 +93,15 @@ struct gb_server {
 
 namespace {
 
-// HBM reserved by a request while it is active: the bucket lists of one of its
-// pieces (a Mertens estimate of the strikes per segment of primes above the
-// bucket bound, times the segments of one piece), plus its segment records.
+// HBM reserved by a request while it is active: the strike bitmaps of one of
+// its pieces when its range reaches primes above the bucket bound (a window
+// of E + H <= E + 32768 bits per segment), plus its segment records.
 uint64_t reservation(const gb_server *s, const Req *r)
 {
-    const double root = std::sqrt((double)r->Bn);
-    const double lb = std::ldexp(1.0, (int)s->lb_log2);
-    double per_seg = 0;
-    if (root > lb)
-        per_seg = (double)(s->seg_evens + 2048) * std::log(std::log(root) / std::log(lb));
     const uint64_t segs = std::min<uint64_t>((r->nE + s->seg_evens - 1) / s->seg_evens,
                                              s->cfg.piece_segments);
-    return (uint64_t)((1.1 * per_seg + 1024.0) * 4.0 * (double)segs) + segs * 64 + 4096;
+    const bool big = std::sqrt((double)r->Bn) > std::ldexp(1.0, (int)s->lb_log2);
+    return (big ? segs * ((s->seg_evens + 32768) / 8) : 0) + segs * 64 + 4096;
 }
 
 void finish(gb_server *s, Req *r, Clock::time_point now)

@@ -24,8 +24,9 @@
 //                    keeps one bit position, so its mask is loop-invariant),
 //                    larger ones one prime per thread;
 //   * primes above the bucket bound (when the launch has buckets) are not
-//                    visited here: the bucket-fill kernel has listed the
-//                    window bits they strike, and the segment clears them.
+//                    visited here: the bucket-fill kernel has set the window
+//                    bits they strike in the segment's strike bitmap in HBM,
+//                    which the presieve folds into the LDS window.
 // Probe (bit-parallel): a thread owns 32 consecutive evens.  For candidate p
 // the 32 bits q = n - p of those evens are 32 consecutive window bits, so one
 // funnel shift of two LDS words tests p against all 32 evens at once; hits are
@@ -165,8 +166,11 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
                 ph[i] = (beta + p - (32u * tid) % p) % p;   // (beta - 32w) mod p at w = tid
                 dec[i] = (32u * NT) % p;
             }
+            // bits struck by the primes above the bucket bound (if any)
+            const uint32_t *__restrict__ bm =
+                a.bitmap ? a.bitmap + (seg - a.seg_base) * (uint64_t)NWr : nullptr;
             for (uint32_t w = tid; w < NWr; w += NT) {
-                uint32_t m = 0;
+                uint32_t m = bm ? bm[w] : 0u;
 #pragma unroll
                 for (int i = 0; i < 10; ++i) {
                     m |= word_pattern(kPre[i]) << ph[i];
@@ -219,19 +223,6 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
                     atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
                 }
             }
-        }
-        // ---- bucket drain: the bits struck by primes above the bound ----
-        if (a.bcap) {
-            const uint64_t rel = seg - a.seg_base;
-            const uint32_t c = a.bcount[rel];
-            const uint32_t lim = c < a.bcap ? c : a.bcap;
-            const uint32_t *__restrict__ bk = a.bucket + rel * a.bcap;
-            for (uint32_t e = tid; e < lim; e += NT) {
-                const uint32_t o = bk[e];
-                atomicAnd(&bits[o >> 5], ~(1u << (o & 31)));
-            }
-            if (tid == 0 && c > a.bcap)
-                atomicMax(a.bover, (unsigned long long)c);
         }
         __syncthreads();
 

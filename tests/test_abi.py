@@ -88,3 +88,12 @@ def test_product_path_has_no_oracle_or_fallback():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert not pat.search(src), f
+
+
+def test_build_flags_keep_miscompiled_forms_out():
+    """The kernels are built without packed fp32 ops and without v_bitop3 (the
+    compiler's fused three-input bitwise ops gave wrong probe masks)."""
+    from paper_2603_07850_amd import build
+    flags = " ".join(build.FLAGS)
+    assert "-target-feature -Xclang -packed-fp32-ops" in flags
+    assert "-target-feature -Xclang -bitop3-insts" in flags
