@@ -75,6 +75,30 @@ def algorithmic_ops_per_even(wm, seg_log2, halo_bits):
     return OPS_PER_WORD_OP * (strikes + tests)
 
 
+KERNEL_SOURCES = ("paper_2603_07850_amd/csrc/gb_sieve.hip", "paper_2603_07850_amd/csrc/gb_arith.h",
+                  "paper_2603_07850_amd/csrc/gb_internal.h")
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, or None when the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "sieve_probe_1e12.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    h = re.search(r"kernel_source_sha256_16: ([0-9a-f]+)", text)
+    if not m or not h:
+        return None
+    sha = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            sha.update(fh.read())
+    return int(m.group(1)) if sha.hexdigest()[:16] == h.group(1) else None
+
+
 def cpu_baseline(sample_windows):
     """The oracle, as it stands, over seeded windows of the headline range."""
     from concurrent.futures import ThreadPoolExecutor
@@ -195,6 +219,8 @@ def main():
     ap.add_argument("--batched", action="store_true")
     ap.add_argument("--served", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--params", default="",
+                    help="seg_log2,wg_size,window,bucket_log2 instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
 
@@ -218,9 +244,12 @@ def main():
     evens = evens_in(A, B)
 
     gb.base_primes(limit)
-    if not args.no_autotune:
+    if args.params:
+        lg, wg, win, blog = (int(x) for x in args.params.split(","))
+        gb.set_params(seg_log2=lg, wg_size=wg, window=win, bucket_log2=blog)
+    elif not args.no_autotune:
         # autotuner: calibration on the top 2*10^10 of the range (results unaffected)
-        params = gb.autotune(B - 4 * 10**10, B, P_max)
+        gb.autotune(B - 4 * 10**10, B, P_max)
     params = gb.get_params()
 
     def step():
@@ -249,7 +278,7 @@ def main():
     kern_s = sum(probe_ms) / len(probe_ms) / 1e3
     achieved = ops_even * evens / kern_s
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": measured_traffic(),
                 "kernel": "sieve_probe_kernel", "kernel_ms": kern_s * 1e3,
                 "ops_per_even": ops_even}
 
@@ -268,6 +297,10 @@ def main():
         "roofline": roofline,
     }
     if args.batched or args.served:
+        # batches reach 2^64: automatic strike-bitmap policy for the other legs
+        p = gb.get_params()
+        p["bucket_log2"] = 0
+        gb.set_params(**p)
         out["batched"] = run_batched(gb, 2)
     if args.served:
         out["served"] = run_served(gb, out["batched"]["batched_evens_per_s"])

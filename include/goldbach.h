@@ -95,7 +95,10 @@ typedef struct gb_result {
  *              maximum that LDS allows.
  *   bucket_log2  primes above 2^bucket_log2 are not sieved segment by segment
  *              but through per-segment strike bitmaps in HBM, filled once per
- *              run of segments; 0 = seg_log2 + 1, else 17..32 (32 = never).
+ *              run of segments; 17..32 (32 = never) applies to every range
+ *              whose isqrt(B) exceeds the bound; 0 = automatic: bound
+ *              2^(seg_log2 + 1), used for ranges whose isqrt(B) exceeds four
+ *              times the bound.
  *   bucket_mib HBM budget for the strike bitmaps of one round, in MiB
  *              (0 = 512); larger batches run in several rounds.
  */

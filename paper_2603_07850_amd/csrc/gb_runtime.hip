@@ -429,7 +429,11 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
             }
             g.nE = (b - a) / 2 + 1;
             g.nseg = (g.nE + E - 1) >> lg;
-            if (root > pl.lb && a > 2 * (uint64_t)pl.H + 2)
+            // automatic bound: strike bitmaps only pay when the root is well
+            // above the bound (for [4, 10^12] the per-segment remainders of the
+            // primes up to 10^6 are cheaper than filling bitmaps)
+            const uint64_t need = pr.bucket_log2 ? pl.lb : 4 * pl.lb;
+            if (root > need && a > 2 * (uint64_t)pl.H + 2)
                 hits[i] = expected_strikes((double)Wbits, (double)pl.lb, (double)root);
         }
         evens += g.nE;
