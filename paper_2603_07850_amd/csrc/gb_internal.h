@@ -77,7 +77,13 @@ struct GbProbeArgs {
     GbIvDone *done;
     const uint32_t *bitmap;   // per segment (E + H)/32 words: bits struck by large
                               // primes; null when the launch has no buckets
+    const uint32_t *ctab;     // probe candidate table, 3 words per candidate
 };
+
+// Probe candidate table: for the odd primes p_k <= 65536 (k = 1, 2, ...),
+// entry k - 1 holds {4 * ceil((p_k >> 1) / 32), (-(p_k >> 1)) mod 32,
+// p_k - p_(k-1) with p_0 = 0}; kCandPad zero entries follow the last one.
+constexpr uint32_t kCandPad = 16;
 
 // A run of consecutive segments of one interval that the bucket-fill kernel
 // treats as one window [Q0, Q0 + 2*dmax] of odd numbers.

@@ -117,6 +117,7 @@ struct Ctx {
     uint64_t T = 0;
     uint64_t nprimes = 0;
     DevBuf primes;
+    DevBuf d_ctab;                // probe candidate table (gb_internal.h)
     std::vector<uint32_t> small;  // host copy of the primes <= 65536 (launch planning)
     gb_params params = {18, 256, 4096, 0, 0, 0};
     uint64_t pi2[33] = {};        // number of table primes <= 2^k
@@ -204,6 +205,7 @@ bool params_valid(const gb_params &p)
 void release_all(Ctx &c)
 {
     c.primes.release();
+    c.d_ctab.release();
     c.d_iv.release();
     c.d_rec.release();
     c.d_spill.release();
@@ -320,6 +322,25 @@ gb_status build_table(Ctx &c, uint64_t limit)
     e = hipMemcpy(c.small.data(), c.primes.p, nsmall * 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
         set_err("prime table copy failed: %s", hipGetErrorString(e));
+        release_all(c);
+        return GB_EHIP;
+    }
+    // probe candidate table from the odd primes <= 65536
+    std::vector<uint32_t> tab(((size_t)nsmall - 1 + kCandPad) * 3, 0u);
+    for (size_t k = 1; k < nsmall; ++k) {
+        const uint32_t pk = c.small[k], h = pk >> 1;
+        uint32_t *t = &tab[(k - 1) * 3];
+        t[0] = ((h + 31) >> 5) << 2;
+        t[1] = (0u - h) & 31;
+        t[2] = pk - (k > 1 ? c.small[k - 1] : 0u);
+    }
+    if ((st = c.d_ctab.reserve(tab.size() * 4)) != GB_OK) {
+        release_all(c);
+        return st;
+    }
+    e = hipMemcpy(c.d_ctab.p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        set_err("candidate table upload failed: %s", hipGetErrorString(e));
         release_all(c);
         return GB_EHIP;
     }
@@ -611,6 +632,7 @@ gb_status enqueue_kernels(Ctx &c, const Plan &pl, uint64_t P_max, const gb_param
         a.claim = claims + ri;
         a.done = (GbIvDone *)c.d_done.p;
         a.bitmap = r.bm ? (const uint32_t *)c.d_bitmap.p : nullptr;
+        a.ctab = (const uint32_t *)c.d_ctab.p;
         const uint32_t g = (uint32_t)std::min<uint64_t>(grid, r.nsegs);
         GB_HIP(gb_launch_probe((int)pr.seg_log2, (int)pr.wg_size, g, a, s));
     }
@@ -639,7 +661,7 @@ std::vector<uint64_t> graph_key(const Ctx &c, const Plan &pl, uint64_t P_max, co
                                 uint32_t grid)
 {
     std::vector<uint64_t> key = {
-        (uint64_t)c.primes.p, (uint64_t)c.d_iv.p, (uint64_t)c.d_rec.p, (uint64_t)c.d_spill.p,
+        (uint64_t)c.primes.p, (uint64_t)c.d_ctab.p, (uint64_t)c.d_iv.p, (uint64_t)c.d_rec.p, (uint64_t)c.d_spill.p,
         (uint64_t)c.d_unres.p, (uint64_t)c.d_res.p, (uint64_t)c.d_ctr.p, (uint64_t)c.d_done.p,
         (uint64_t)c.d_bitmap.p, (uint64_t)pl.words, (uint64_t)c.d_chunk.p,
         (uint64_t)c.d_claims.p, (uint64_t)c.d_task.p, pl.chunks.size(), c.nprimes, pl.iv.size(),

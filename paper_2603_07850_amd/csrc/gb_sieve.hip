@@ -43,9 +43,46 @@ constexpr uint32_t kPre[10] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
 constexpr uint32_t kHaloMax = 32768;  // largest halo: candidates up to 65536
 constexpr uint32_t kFirstStrided = 11;  // primes[11] == 37
 
-// The prime table seen through the constant address space: loads with a
-// uniform index compile to scalar loads.
+// One probe candidate: the byte offset of the LDS word holding bit(n - p)
+// below the word of bit(n), the funnel-shift amount that aligns the 32 bits
+// n - p of a lane's 32 evens, and the gap to the previous candidate.
+struct Cand {
+    uint32_t off, sh, gap;
+};
+struct CandGroup {
+    Cand c[4];
+};
+// The candidate and prime tables seen through the constant address space:
+// loads with a uniform index compile to scalar loads.
+typedef const __attribute__((address_space(4))) Cand *ccand_t;
+typedef const __attribute__((address_space(4))) CandGroup *cgroup_t;
 typedef const __attribute__((address_space(4))) uint32_t *cprime_t;
+
+// Test one candidate against a lane's open evens u (bit i: even n0 + 64j + 2i):
+// x holds the primality bits of the 32 numbers n - p; the hits leave u.
+__device__ __forceinline__ void probe_one(const char *lds, uint32_t base4, uint32_t off,
+                                          uint32_t sh, uint32_t gap, uint32_t &u, uint32_t &acc)
+{
+    const uint32_t addr = base4 - off;
+    const uint32_t lo = *(const uint32_t *)(lds + addr);
+    const uint32_t hi = *(const uint32_t *)(lds + addr + 4);
+    const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, sh);
+    acc = __umul24(gap, (uint32_t)__popc(u)) + acc;
+    u &= ~x;
+}
+
+__device__ __forceinline__ void probe_group(const char *lds, uint32_t base4, cgroup_t G,
+                                            uint32_t k, uint32_t &u, uint32_t &acc,
+                                            uint32_t &lastg, uint32_t &ulast)
+{
+    const uint32_t ustart = u;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        probe_one(lds, base4, G->c[t].off, G->c[t].sh, G->c[t].gap, u, acc);
+    const bool any = u != ustart;
+    lastg = any ? k : lastg;
+    ulast = any ? ustart : ulast;
+}
 
 __host__ __device__ constexpr uint32_t word_pattern(uint32_t p)
 {
@@ -227,9 +264,18 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
         __syncthreads();
 
         // ---- probe ----
-        // Candidates are read through the constant address space so that the
-        // uniform index k becomes scalar loads; the per-candidate work is then
-        // one LDS pair read, a funnel shift and four integer ops per lane.
+        // Candidate k (p = primes[k], k >= 1) comes from the candidate table as
+        // three words: the byte offset of the word holding bit(n - p) below the
+        // lane's word, the funnel-shift amount and the gap p_k - p_(k-1)
+        // (p_0 = 0); four candidates make one 48-byte group, read with two
+        // scalar loads.  The per-candidate lane work is one LDS
+        // pair read, a funnel shift, a popcount, a multiply-add and a mask
+        // update.  The checksum of a block is accumulated in gap form: the sum
+        // of p_min over the evens resolved by candidates 1..K equals the sum
+        // over k of gap_k * (evens open before k), minus p_K per even still
+        // open after K.
+        const cgroup_t gt = (cgroup_t)a.ctab;
+        const ccand_t ct = (ccand_t)a.ctab;
         const cprime_t cp = (cprime_t)primes;
         const uint32_t ncand = a.ncand;
         const uint32_t ngrp = ncand >> 2;
@@ -258,62 +304,35 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
             }
             const uint32_t u0 = u;
             const uint32_t base4 = ((act ? j : 0) + H32) * 4;  // byte address of the lane's word
-            uint32_t sum32 = 0;   // < 32 * 2^16 per block
+            uint32_t acc = 0;     // gap-form checksum, < 32 * 2^16 per block
             uint32_t lastg = 0;   // first candidate of the last group with a hit
             uint32_t ulast = 0;   // open evens at the start of that group
-            uint32_t k = 1;
-            // candidates of the next group are loaded one group ahead
-            uint32_t pn[4];
-#pragma unroll
-            for (uint32_t t = 0; t < 4; ++t)
-                pn[t] = cp[1 + t < ncand ? 1 + t : ncand];
-            for (uint32_t g = 0; g < ngrp; ++g, k += 4) {
-                const uint32_t ustart = u;
-                uint32_t pc[4];
-#pragma unroll
-                for (uint32_t t = 0; t < 4; ++t) {
-                    pc[t] = pn[t];
-                    const uint32_t kn = k + 4 + t;
-                    pn[t] = cp[kn < ncand ? kn : ncand];
-                }
-#pragma unroll
-                for (uint32_t t = 0; t < 4; ++t) {
-                    const uint32_t p = pc[t];
-                    const uint32_t h = p >> 1;
-                    const uint32_t addr = base4 - (((h + 31) >> 5) << 2);
-                    const uint32_t lo = *(const uint32_t *)(lds + addr);
-                    const uint32_t hi = *(const uint32_t *)(lds + addr + 4);
-                    const uint32_t hit = __builtin_amdgcn_alignbit(hi, lo, (0u - h) & 31) & u;
-                    u ^= hit;
-                    sum32 = __umul24(p, (uint32_t)__popc(hit)) + sum32;
-                }
-                const bool any = u != ustart;
-                lastg = any ? k : lastg;
-                ulast = any ? ustart : ulast;
-                if (__ballot(u != 0) == 0) {
-                    k += 4;
+            uint32_t k = 1;       // next candidate
+            // groups of four; the group's table words arrive with two scalar loads
+            for (uint32_t g = 0; g < ngrp; ++g) {
+                probe_group(lds, base4, gt + g, k, u, acc, lastg, ulast);
+                k += 4;
+                if (__ballot(u != 0) == 0)
                     break;
-                }
             }
+            // the candidates after the last full group, one at a time
             if (__ballot(u != 0) != 0) {
                 for (; k <= ncand; ++k) {
                     const uint32_t ustart = u;
-                    const uint32_t p = cp[k];
-                    const uint32_t h = p >> 1;
-                    const uint32_t addr = base4 - (((h + 31) >> 5) << 2);
-                    const uint32_t lo = *(const uint32_t *)(lds + addr);
-                    const uint32_t hi = *(const uint32_t *)(lds + addr + 4);
-                    const uint32_t hit = __builtin_amdgcn_alignbit(hi, lo, (0u - h) & 31) & u;
-                    u ^= hit;
-                    sum32 = __umul24(p, (uint32_t)__popc(hit)) + sum32;
+                    probe_one(lds, base4, ct[k - 1].off, ct[k - 1].sh, ct[k - 1].gap, u, acc);
                     const bool any = u != ustart;
                     lastg = any ? k : lastg;
                     ulast = any ? ustart : ulast;
-                    if (__ballot(u != 0) == 0)
+                    if (__ballot(u != 0) == 0) {
+                        ++k;
                         break;
+                    }
                 }
             }
-            sum += sum32;
+            // k - 1 is the last candidate the wave tested
+            if (u && k > 1)
+                acc -= cp[k - 1] * (uint32_t)__popc(u);
+            sum += acc;
             nres += (uint32_t)(__popc(u0) - __popc(u));
             // Replay the last group with a hit: its last hitting candidate is
             // the block's largest p_min, and the lowest bit of that hit is the
@@ -322,16 +341,16 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
             if (lastg) {
                 uint32_t uu = ulast, lastp = 0, lasth = 0;
                 const uint32_t kend = lastg + 3 < ncand ? lastg + 3 : ncand;
+                const uint32_t *tab = a.ctab;
                 for (uint32_t kk = lastg; kk <= kend && uu; ++kk) {
-                    const uint32_t p = primes[kk];
-                    const uint32_t h = p >> 1;
-                    const uint32_t addr = base4 - (((h + 31) >> 5) << 2);
+                    const uint32_t *e = tab + 3 * (kk - 1);
+                    const uint32_t addr = base4 - e[0];
                     const uint32_t lo = *(const uint32_t *)(lds + addr);
                     const uint32_t hi = *(const uint32_t *)(lds + addr + 4);
-                    const uint32_t hit = __builtin_amdgcn_alignbit(hi, lo, (0u - h) & 31) & uu;
+                    const uint32_t hit = __builtin_amdgcn_alignbit(hi, lo, e[1]) & uu;
                     if (hit) {
                         uu ^= hit;
-                        lastp = p;
+                        lastp = primes[kk];
                         lasth = hit;
                     }
                 }
