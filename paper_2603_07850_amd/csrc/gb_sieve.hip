@@ -19,10 +19,10 @@
 // Sieve (every q is odd):
 //   * primes 3..31   periodic 32-bit word masks, one word write per 32 odds;
 //   * primes >= 37   strided clears from max(p^2, first multiple in the
-//                    window) with LDS atomic AND; primes up to E/NT are
-//                    cleared cooperatively by the whole workgroup (each thread
-//                    keeps one bit position, so its mask is loop-invariant),
-//                    larger ones one prime per thread;
+//                    window) with LDS atomic AND; primes up to E/1024 are
+//                    cleared by one wave each (each lane keeps one bit
+//                    position, so its mask is loop-invariant), larger ones one
+//                    prime per thread with several table loads in flight;
 //   * primes above the bucket bound (when the launch has buckets) are not
 //                    visited here: the bucket-fill kernel has set the window
 //                    bits they strike in the segment's strike bitmap in HBM,
@@ -42,6 +42,7 @@ namespace {
 constexpr uint32_t kPre[10] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
 constexpr uint32_t kHaloMax = 32768;  // largest halo: candidates up to 65536
 constexpr uint32_t kFirstStrided = 11;  // primes[11] == 37
+constexpr uint32_t kPrimesInFlight = 8;  // thread-tier table loads issued together
 
 // One probe candidate: the byte offset of the LDS word holding bit(n - p)
 // below the word of bit(n), the funnel-shift amount that aligns the 32 bits
@@ -116,6 +117,36 @@ __device__ __forceinline__ uint32_t first_bit(uint64_t qlo, uint64_t qneg, bool 
     return j > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)j;
 }
 
+// First window bit as above for a window start 0 < q_lo < 2^52, which a
+// double holds exactly (qd = q_lo, qlo32 = its low word, sq = isqrt(q_lo)),
+// and p < 2^26: one double quotient estimate, within one of floor(q_lo / p),
+// and an exact fma remainder in (-p, 2p) that one step corrects.  When
+// p > sq, p^2 lies past q_lo by less than the window, so the distance fits
+// 32 bits.
+__device__ __forceinline__ uint32_t first_bit_d(double qd, uint32_t qlo32, uint32_t sq, uint32_t p)
+{
+    const double pd = (double)p;
+    double inv = __builtin_amdgcn_rcp(pd);
+    double e = __builtin_fma(-pd, inv, 1.0);
+    inv = __builtin_fma(inv, e, inv);
+    e = __builtin_fma(-pd, inv, 1.0);
+    inv = __builtin_fma(inv, e, inv);
+    const double qt = __builtin_floor(qd * inv);
+    int32_t r = (int32_t)__builtin_fma(-qt, pd, qd);
+    r += r < 0 ? (int32_t)p : 0;
+    r -= r >= (int32_t)p ? (int32_t)p : 0;
+    const uint32_t x = r ? p - (uint32_t)r : 0u;  // -q_lo mod p
+    uint32_t j = (x & 1) ? (x >> 1) + (p >> 1) + 1 : (x >> 1);
+    const uint32_t jsq = (p * p - qlo32) >> 1;
+    return (p > sq && jsq > j) ? jsq : j;
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+           __builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+
 // Number of table entries <= x (upper bound), x < 2^32.
 __device__ __forceinline__ uint32_t count_le(const uint32_t *primes, uint64_t nprimes, uint32_t x)
 {
@@ -126,6 +157,41 @@ __device__ __forceinline__ uint32_t count_le(const uint32_t *primes, uint64_t np
             lo = mid + 1;
         else
             hi = mid;
+    }
+    return (uint32_t)lo;
+}
+
+// Clear the window bits j, j + p, ... below weff (one prime, one thread).
+__device__ __forceinline__ void strike_prime(uint32_t *bits, uint32_t weff, uint32_t p, uint32_t j)
+{
+    if (p < weff) {
+        for (uint32_t jj = j; jj < weff; jj += p)
+            atomicAnd(&bits[jj >> 5], ~(1u << (jj & 31)));
+    } else if (j < weff) {
+        atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
+    }
+}
+
+// The same count found by one wave: each round its 64 lanes test 64 evenly
+// spaced entries of the bracket that holds the answer, and the ballot of the
+// (monotone) outcomes narrows the bracket 64-fold.  Uniform result.
+__device__ __forceinline__ uint32_t count_le_wave(const uint32_t *primes, uint64_t nprimes,
+                                                 uint32_t x, uint32_t lane)
+{
+    uint64_t lo = 0, hi = nprimes;   // the count lies in [lo, hi]
+    while (lo < hi) {
+        const uint64_t step = (hi - lo + 63) >> 6;
+        const uint64_t idx = lo + (uint64_t)lane * step;
+        const bool le = idx < hi && primes[idx] <= x;
+        const uint32_t L = (uint32_t)__popcll(__ballot(le));
+        if (L == 0) {
+            hi = lo;
+        } else {
+            const uint64_t nlo = lo + (uint64_t)(L - 1) * step + 1;
+            const uint64_t nhi = lo + (uint64_t)L * step;
+            lo = nlo;
+            hi = nhi < hi ? nhi : hi;
+        }
     }
     return (uint32_t)lo;
 }
@@ -142,9 +208,11 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
     constexpr uint64_t E = 1ull << LOG2E;
     constexpr uint32_t NW = (uint32_t)((E + kHaloMax) / 32);
     constexpr uint32_t NWAVE = NT / 64;
-    constexpr uint32_t PS = (uint32_t)(E / NT);  // cooperative-clear bound
+    // primes up to this bound strike a window >= 1024 times: one wave each
+    constexpr uint32_t kWaveTierMax = (uint32_t)(E >> 9);
     __shared__ uint32_t bits[NW];
     __shared__ unsigned long long sh_seg;
+    __shared__ uint32_t sh_nroot;
     __shared__ unsigned long long red_sum[NWAVE];
     __shared__ uint32_t red_cnt[NWAVE];
     __shared__ uint32_t red_p[NWAVE];
@@ -157,12 +225,15 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
     const uint32_t H32 = H >> 5;
     const uint32_t NWr = (uint32_t)((E + H) >> 5);  // window words in use
     const uint32_t *__restrict__ primes = a.primes;
+    const cprime_t cp = (cprime_t)primes;
+    // primes[kFirstStrided .. nwave) are cleared one prime per wave
+    const uint32_t nwave = count_le(primes, a.nprimes, kWaveTierMax);
 
     for (;;) {
         if (tid == 0)
             sh_seg = atomicAdd(a.claim, 1ull);
         __syncthreads();
-        const uint64_t claim = sh_seg;
+        const uint64_t claim = uniform64(sh_seg);
         if (claim >= a.nsegs)
             break;
         const uint64_t seg = a.seg_base + claim;
@@ -187,9 +258,15 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
         const uint64_t qlo = n0 - 1 - 2ull * H;     // valid when !neg
         const uint64_t qneg = 2ull * H + 1 - n0;    // valid when neg
         const uint64_t qhi = n0 + 2ull * cnt - 5;   // largest q any n of the segment needs
-        const uint32_t nroot = count_le(primes, a.nprimes, gb_isqrt64(qhi));
-        const uint32_t nsieve = nroot < a.lb_count ? nroot : a.lb_count;  // primes cleared here
-        const uint32_t ncoop = count_le(primes, a.nprimes, PS);
+        // windows starting in (0, 2^52) take the double-precision first-bit path
+        const bool small = !neg && qlo < (1ull << 52);
+        const double qd = (double)qlo;
+        const uint32_t sq = small ? gb_isqrt64(qlo) : 0u;
+        if (wave == 0) {
+            const uint32_t c = count_le_wave(primes, a.nprimes, gb_isqrt64(qhi), lane);
+            if (lane == 0)
+                sh_nroot = c;
+        }
 
         // ---- presieve: periodic masks of 3..31 ----
         {
@@ -234,30 +311,50 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
         }
         __syncthreads();
 
-        // ---- strided clears, cooperative tier: 37 <= p <= E/NT ----
+        const uint32_t nroot = __builtin_amdgcn_readfirstlane(sh_nroot);  // published by the barrier above
+        const uint32_t nsieve = nroot < a.lb_count ? nroot : a.lb_count;  // primes cleared here
         const uint32_t wend = (weff + 31) >> 5;
-        const uint32_t coop_end = ncoop < nsieve ? ncoop : nsieve;
-        for (uint32_t i = kFirstStrided; i < coop_end; ++i) {
-            const uint32_t p = primes[i];
-            const uint64_t jt = (uint64_t)first_bit(qlo, qneg, neg, p) + (uint64_t)tid * p;
-            if (jt < weff) {
-                const uint32_t mask = ~(1u << (jt & 31));
-                const uint32_t step = (NT / 32) * p;
-                for (uint32_t w = (uint32_t)(jt >> 5); w < wend; w += step)
-                    atomicAnd(&bits[w], mask);
+
+        // ---- strided clears, one prime per wave: 37 <= p <= kWaveTierMax ----
+        // Lane l strikes bits j0 + l*p + m*64p; 64p is a multiple of 32, so a
+        // lane's bit position within its words, and its mask, never change.
+        {
+            const uint32_t wv = __builtin_amdgcn_readfirstlane(wave);
+            const uint32_t wave_end = nwave < nsieve ? nwave : nsieve;
+            for (uint32_t i = kFirstStrided + wv; i < wave_end; i += NWAVE) {
+                const uint32_t p = cp[i];
+                const uint32_t j0 = small ? first_bit_d(qd, (uint32_t)qlo, sq, p)
+                                          : first_bit(qlo, qneg, neg, p);
+                const uint64_t jt = (uint64_t)j0 + (uint64_t)lane * p;
+                if (jt < weff) {
+                    const uint32_t mask = ~(1u << (jt & 31));
+                    const uint32_t step = 2 * p;  // words per 64p bits
+                    for (uint32_t w = (uint32_t)(jt >> 5); w < wend; w += step)
+                        atomicAnd(&bits[w], mask);
+                }
             }
         }
-        // ---- strided clears, one prime per thread: E/NT < p <= min(isqrt(q_hi), bound) ----
+        // ---- strided clears, one prime per thread: kWaveTierMax < p <= min(isqrt(q_hi), bound) ----
+        // kPrimesInFlight table loads are issued before the first is used.
         {
-            const uint32_t first = coop_end > kFirstStrided ? coop_end : kFirstStrided;
-            for (uint32_t i = first + tid; i < nsieve; i += NT) {
-                const uint32_t p = primes[i];
-                const uint32_t j = first_bit(qlo, qneg, neg, p);
-                if (p < weff) {
-                    for (uint32_t jj = j; jj < weff; jj += p)
-                        atomicAnd(&bits[jj >> 5], ~(1u << (jj & 31)));
-                } else if (j < weff) {
-                    atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
+            const uint32_t first = nwave > kFirstStrided ? nwave : kFirstStrided;
+            for (uint32_t i0 = first + tid; i0 < nsieve; i0 += kPrimesInFlight * NT) {
+                uint32_t pv[kPrimesInFlight];
+#pragma unroll
+                for (uint32_t t = 0; t < kPrimesInFlight; ++t) {
+                    const uint32_t ii = i0 + t * NT;
+                    pv[t] = ii < nsieve ? primes[ii] : 0u;
+                }
+                if (small) {
+#pragma unroll
+                    for (uint32_t t = 0; t < kPrimesInFlight; ++t)
+                        if (pv[t])
+                            strike_prime(bits, weff, pv[t], first_bit_d(qd, (uint32_t)qlo, sq, pv[t]));
+                } else {
+#pragma unroll
+                    for (uint32_t t = 0; t < kPrimesInFlight; ++t)
+                        if (pv[t])
+                            strike_prime(bits, weff, pv[t], first_bit(qlo, qneg, neg, pv[t]));
                 }
             }
         }
@@ -276,7 +373,6 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
         // open after K.
         const cgroup_t gt = (cgroup_t)a.ctab;
         const ccand_t ct = (ccand_t)a.ctab;
-        const cprime_t cp = (cprime_t)primes;
         const uint32_t ncand = a.ncand;
         const uint32_t ngrp = ncand >> 2;
         const char *lds = (const char *)bits;
