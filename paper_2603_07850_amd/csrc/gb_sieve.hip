@@ -27,9 +27,9 @@
 //                    visited here: the bucket-fill kernel has set the window
 //                    bits they strike in the segment's strike bitmap in HBM,
 //                    which the presieve folds into the LDS window.
-// Probe (bit-parallel): a thread owns 32 consecutive evens.  For candidate p
-// the 32 bits q = n - p of those evens are 32 consecutive window bits, so one
-// funnel shift of two LDS words tests p against all 32 evens at once; hits are
+// Probe (bit-parallel): a thread owns 64 consecutive evens.  For candidate p
+// the 64 bits q = n - p of those evens are 64 consecutive window bits, so two
+// funnel shifts of three LDS words test p against all 64 evens at once; hits are
 // removed from the thread's unresolved mask and the wave stops when no lane
 // has an unresolved even left.  Ascending p makes the first hit the minimal
 // one.  Evens still open after the window are appended to the spill list for
@@ -45,8 +45,8 @@ constexpr uint32_t kFirstStrided = 11;  // primes[11] == 37
 constexpr uint32_t kPrimesInFlight = 8;  // thread-tier table loads issued together
 
 // One probe candidate: the byte offset of the LDS word holding bit(n - p)
-// below the word of bit(n), the funnel-shift amount that aligns the 32 bits
-// n - p of a lane's 32 evens, and the gap to the previous candidate.
+// below the word of bit(n), the funnel-shift amount that aligns the bits
+// n - p of a lane's evens, and the gap to the previous candidate.
 struct Cand {
     uint32_t off, sh, gap;
 };
@@ -59,30 +59,37 @@ typedef const __attribute__((address_space(4))) Cand *ccand_t;
 typedef const __attribute__((address_space(4))) CandGroup *cgroup_t;
 typedef const __attribute__((address_space(4))) uint32_t *cprime_t;
 
-// Test one candidate against a lane's open evens u (bit i: even n0 + 64j + 2i):
-// x holds the primality bits of the 32 numbers n - p; the hits leave u.
+// Test one candidate against a lane's 64 open evens (ul, uh; bit i: even
+// n0 + 128j + 2i): xl, xh hold the primality bits of the 64 numbers n - p,
+// funnel-shifted out of three LDS words; the hits leave the open masks.
 __device__ __forceinline__ void probe_one(const char *lds, uint32_t base4, uint32_t off,
-                                          uint32_t sh, uint32_t gap, uint32_t &u, uint32_t &acc)
+                                          uint32_t sh, uint32_t gap, uint32_t &ul, uint32_t &uh,
+                                          uint32_t &acc)
 {
     const uint32_t addr = base4 - off;
-    const uint32_t lo = *(const uint32_t *)(lds + addr);
-    const uint32_t hi = *(const uint32_t *)(lds + addr + 4);
-    const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, sh);
-    acc = __umul24(gap, (uint32_t)__popc(u)) + acc;
-    u &= ~x;
+    const uint32_t w0 = *(const uint32_t *)(lds + addr);
+    const uint32_t w1 = *(const uint32_t *)(lds + addr + 4);
+    const uint32_t w2 = *(const uint32_t *)(lds + addr + 8);
+    const uint32_t xl = __builtin_amdgcn_alignbit(w1, w0, sh);
+    const uint32_t xh = __builtin_amdgcn_alignbit(w2, w1, sh);
+    acc = __umul24(gap, (uint32_t)(__popc(ul) + __popc(uh))) + acc;
+    ul &= ~xl;
+    uh &= ~xh;
 }
 
 __device__ __forceinline__ void probe_group(const char *lds, uint32_t base4, cgroup_t G,
-                                            uint32_t k, uint32_t &u, uint32_t &acc,
-                                            uint32_t &lastg, uint32_t &ulast)
+                                            uint32_t k, uint32_t &ul, uint32_t &uh,
+                                            uint32_t &acc, uint32_t &lastg, uint32_t &gl,
+                                            uint32_t &gh)
 {
-    const uint32_t ustart = u;
+    const uint32_t sl = ul, sh = uh;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
-        probe_one(lds, base4, G->c[t].off, G->c[t].sh, G->c[t].gap, u, acc);
-    const bool any = u != ustart;
+        probe_one(lds, base4, G->c[t].off, G->c[t].sh, G->c[t].gap, ul, uh, acc);
+    const bool any = (ul != sl) | (uh != sh);
     lastg = any ? k : lastg;
-    ulast = any ? ustart : ulast;
+    gl = any ? sl : gl;
+    gh = any ? sh : gh;
 }
 
 __host__ __device__ constexpr uint32_t word_pattern(uint32_t p)
@@ -202,8 +209,19 @@ __device__ __forceinline__ bool small_prime_35(int64_t q)
            q == 29 || q == 31;
 }
 
+// Waves per SIMD that the LDS window allows (160 KB of LDS per CU, four SIMDs,
+// at most eight waves each): the register budget is set to match it.
+constexpr uint32_t lds_waves_per_simd(int log2e, int nt)
+{
+    const uint32_t wg_bytes = (uint32_t)(((1u << log2e) + kHaloMax) / 8) + 1024;
+    const uint32_t wgs = (160u * 1024u) / wg_bytes;
+    const uint32_t w = wgs * (uint32_t)(nt / 64) / 4;
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
 template <int LOG2E, int NT>
-__global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
+__global__ __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_probe_kernel(GbProbeArgs a)
 {
     constexpr uint64_t E = 1ull << LOG2E;
     constexpr uint32_t NW = (uint32_t)((E + kHaloMax) / 32);
@@ -361,22 +379,23 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
         __syncthreads();
 
         // ---- probe ----
-        // Candidate k (p = primes[k], k >= 1) comes from the candidate table as
-        // three words: the byte offset of the word holding bit(n - p) below the
-        // lane's word, the funnel-shift amount and the gap p_k - p_(k-1)
-        // (p_0 = 0); four candidates make one 48-byte group, read with two
-        // scalar loads.  The per-candidate lane work is one LDS
-        // pair read, a funnel shift, a popcount, a multiply-add and a mask
-        // update.  The checksum of a block is accumulated in gap form: the sum
-        // of p_min over the evens resolved by candidates 1..K equals the sum
-        // over k of gap_k * (evens open before k), minus p_K per even still
-        // open after K.
+        // A lane owns a block of 64 consecutive evens, n0 + 128j + 2i for
+        // i < 64, as two mask words (lo: i < 32).  Candidate k (p = primes[k],
+        // k >= 1) comes from the candidate table as three words: the byte
+        // offset of the word holding bit(n - p) below the lane's first word,
+        // the funnel-shift amount and the gap p_k - p_(k-1) (p_0 = 0); four
+        // candidates make one 48-byte group, read with two scalar loads.  Per
+        // candidate a lane reads three LDS words, funnel-shifts the 64 bits
+        // n - p of its evens, counts its open evens and removes the hits.  The
+        // checksum of a block is accumulated in gap form: the sum of p_min
+        // over the evens resolved by candidates 1..K equals the sum over k of
+        // gap_k * (evens open before k), minus p_K per even still open after K.
         const cgroup_t gt = (cgroup_t)a.ctab;
         const ccand_t ct = (ccand_t)a.ctab;
         const uint32_t ncand = a.ncand;
         const uint32_t ngrp = ncand >> 2;
         const char *lds = (const char *)bits;
-        const uint32_t nblk = (cnt + 31) >> 5;
+        const uint32_t nblk = (cnt + 63) >> 6;
         uint64_t sum = 0;
         uint32_t nres = 0;
         uint32_t bestp = 0;
@@ -390,77 +409,98 @@ __global__ __launch_bounds__(NT) void sieve_probe_kernel(GbProbeArgs a)
         for (uint32_t jb = 0; jb < nblk; jb += NT) {
             const uint32_t j = jb + tid;
             const bool act = j < nblk;
-            uint32_t u = 0;
+            uint32_t ul = 0, uh = 0;
             if (act) {
-                u = 0xFFFFFFFFu;
-                if (j == nblk - 1 && (cnt & 31))
-                    u = (1u << (cnt & 31)) - 1;
+                ul = 0xFFFFFFFFu;
+                uh = 0xFFFFFFFFu;
+                const uint32_t r = cnt & 63;
+                if (j == nblk - 1 && r) {
+                    if (r < 32) {
+                        ul = (1u << r) - 1;
+                        uh = 0;
+                    } else {
+                        uh = r == 32 ? 0u : (1u << (r - 32)) - 1;
+                    }
+                }
                 if (n0 == 4 && j == 0)
-                    u &= ~1u;
+                    ul &= ~1u;
             }
-            const uint32_t u0 = u;
-            const uint32_t base4 = ((act ? j : 0) + H32) * 4;  // byte address of the lane's word
-            uint32_t acc = 0;     // gap-form checksum, < 32 * 2^16 per block
+            const uint32_t open0 = (uint32_t)(__popc(ul) + __popc(uh));
+            const uint32_t base4 = ((act ? 2 * j : 0) + H32) * 4;  // byte address of the lane's first word
+            uint32_t acc = 0;     // gap-form checksum, < 64 * 2^16 per block
             uint32_t lastg = 0;   // first candidate of the last group with a hit
-            uint32_t ulast = 0;   // open evens at the start of that group
+            uint32_t gl = 0;      // open evens at the start of that group
+            uint32_t gh = 0;
             uint32_t k = 1;       // next candidate
-            // groups of four; the group's table words arrive with two scalar loads
             for (uint32_t g = 0; g < ngrp; ++g) {
-                probe_group(lds, base4, gt + g, k, u, acc, lastg, ulast);
+                probe_group(lds, base4, gt + g, k, ul, uh, acc, lastg, gl, gh);
                 k += 4;
-                if (__ballot(u != 0) == 0)
+                if (__ballot((ul | uh) != 0) == 0)
                     break;
             }
             // the candidates after the last full group, one at a time
-            if (__ballot(u != 0) != 0) {
+            if (__ballot((ul | uh) != 0) != 0) {
                 for (; k <= ncand; ++k) {
-                    const uint32_t ustart = u;
-                    probe_one(lds, base4, ct[k - 1].off, ct[k - 1].sh, ct[k - 1].gap, u, acc);
-                    const bool any = u != ustart;
+                    const uint32_t sl = ul, sh = uh;
+                    probe_one(lds, base4, ct[k - 1].off, ct[k - 1].sh, ct[k - 1].gap, ul, uh, acc);
+                    const bool any = (ul != sl) | (uh != sh);
                     lastg = any ? k : lastg;
-                    ulast = any ? ustart : ulast;
-                    if (__ballot(u != 0) == 0) {
+                    gl = any ? sl : gl;
+                    gh = any ? sh : gh;
+                    if (__ballot((ul | uh) != 0) == 0) {
                         ++k;
                         break;
                     }
                 }
             }
             // k - 1 is the last candidate the wave tested
-            if (u && k > 1)
-                acc -= cp[k - 1] * (uint32_t)__popc(u);
+            const uint32_t open = (uint32_t)(__popc(ul) + __popc(uh));
+            if (open && k > 1)
+                acc -= cp[k - 1] * open;
             sum += acc;
-            nres += (uint32_t)(__popc(u0) - __popc(u));
+            nres += open0 - open;
             // Replay the last group with a hit: its last hitting candidate is
             // the block's largest p_min, and the lowest bit of that hit is the
             // smallest n attaining it.  Every candidate replayed here was also
             // tested above, so the replay reproduces the same hits.
             if (lastg) {
-                uint32_t uu = ulast, lastp = 0, lasth = 0;
+                uint32_t vl = gl, vh = gh, lastp = 0, hl = 0, hh = 0;
                 const uint32_t kend = lastg + 3 < ncand ? lastg + 3 : ncand;
                 const uint32_t *tab = a.ctab;
-                for (uint32_t kk = lastg; kk <= kend && uu; ++kk) {
+                for (uint32_t kk = lastg; kk <= kend && (vl | vh); ++kk) {
                     const uint32_t *e = tab + 3 * (kk - 1);
                     const uint32_t addr = base4 - e[0];
-                    const uint32_t lo = *(const uint32_t *)(lds + addr);
-                    const uint32_t hi = *(const uint32_t *)(lds + addr + 4);
-                    const uint32_t hit = __builtin_amdgcn_alignbit(hi, lo, e[1]) & uu;
-                    if (hit) {
-                        uu ^= hit;
+                    const uint32_t w0 = *(const uint32_t *)(lds + addr);
+                    const uint32_t w1 = *(const uint32_t *)(lds + addr + 4);
+                    const uint32_t w2 = *(const uint32_t *)(lds + addr + 8);
+                    const uint32_t xl = __builtin_amdgcn_alignbit(w1, w0, e[1]) & vl;
+                    const uint32_t xh = __builtin_amdgcn_alignbit(w2, w1, e[1]) & vh;
+                    if (xl | xh) {
+                        vl ^= xl;
+                        vh ^= xh;
                         lastp = primes[kk];
-                        lasth = hit;
+                        hl = xl;
+                        hh = xh;
                     }
                 }
                 if (lastp > bestp) {
                     bestp = lastp;
-                    bestn = n0 + 64ull * j + 2ull * (uint32_t)(__ffs(lasth) - 1);
+                    const uint32_t bit = hl ? (uint32_t)(__ffs(hl) - 1) : 32u + (uint32_t)(__ffs(hh) - 1);
+                    bestn = n0 + 128ull * j + 2ull * bit;
                 }
             }
-            while (u) {
-                const uint32_t b = __ffs(u) - 1;
-                u &= u - 1;
+            while (ul | uh) {
+                uint32_t bit;
+                if (ul) {
+                    bit = __ffs(ul) - 1;
+                    ul &= ul - 1;
+                } else {
+                    bit = 32 + __ffs(uh) - 1;
+                    uh &= uh - 1;
+                }
                 const unsigned long long idx = atomicAdd(&a.ctr->spills, 1ull);
                 if (idx < a.spill_cap) {
-                    a.spill[idx].n = n0 + 64ull * j + 2ull * b;
+                    a.spill[idx].n = n0 + 128ull * j + 2ull * bit;
                     a.spill[idx].iv = ivx;
                     a.spill[idx].p = 0;
                 }
