@@ -120,7 +120,7 @@ def cpu_baseline(sample_windows):
                       % (len(wins), ev, cores, dt)}
 
 
-def run_batched(gb, steps):
+def run_batched(gb, steps, per_interval=True):
     """4096 seeded uneven intervals: one persistent launch vs one launch each."""
     import statistics
 
@@ -134,6 +134,11 @@ def run_batched(gb, steps):
         res = gb.verify_batch(ivs, 65536)
     dt = (time.perf_counter() - t0) / steps
     lat = gb.last_batch_latencies()
+    q = lambda xs, p: sorted(xs)[min(len(xs) - 1, int(p * len(xs)))]
+    if not per_interval:
+        return {"intervals": len(ivs), "evens": ev, "batched_evens_per_s": ev / dt,
+                "batched_s": dt, "p50_ms": q(lat, 0.5) * 1e3, "p99_ms": q(lat, 0.99) * 1e3,
+                "all_verified": all(r["n_failed"] == 0 for r in res)}
     log("batched: %d intervals in %.3f s per launch; per-interval baseline next" % (len(ivs), dt))
     t0 = time.perf_counter()
     done = []
@@ -143,7 +148,6 @@ def run_batched(gb, steps):
         if i % 256 == 255:
             log("per-interval: %d / %d after %.1f s" % (i + 1, len(ivs), done[-1]))
     dt1 = done[-1]
-    q = lambda xs, p: sorted(xs)[min(len(xs) - 1, int(p * len(xs)))]
     return {
         "intervals": len(ivs), "evens": ev,
         "batched_evens_per_s": ev / dt, "batched_s": dt,
@@ -215,13 +219,15 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-windows", type=int, default=96)
+    ap.add_argument("--cpu-windows", type=int, default=256)
     ap.add_argument("--batched", action="store_true")
     ap.add_argument("--served", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--params", default="",
                     help="seg_log2,wg_size,window,bucket_log2 instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched launch (for profiling); needs --params")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -240,6 +246,13 @@ def main():
         return
 
     import paper_2603_07850_amd as gb
+    if args.batched_only:
+        lg, wg, win, blog = (int(x) for x in args.params.split(","))
+        gb.base_primes(2**32 - 1)
+        gb.set_params(seg_log2=lg, wg_size=wg, window=win, bucket_log2=blog)
+        print(json.dumps({"batched": run_batched(gb, args.steps, per_interval=False),
+                          "params": gb.get_params()}), flush=True)
+        return
     A, B, P_max, limit = HEADLINE["A"], HEADLINE["B"], HEADLINE["P_max"], HEADLINE["limit"]
     evens = evens_in(A, B)
 
