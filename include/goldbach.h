@@ -97,8 +97,7 @@ typedef struct gb_result {
  *              but through per-segment strike bitmaps in HBM, filled once per
  *              run of segments; 17..32 (32 = never) applies to every range
  *              whose isqrt(B) exceeds the bound; 0 = automatic: bound
- *              2^(seg_log2 + 1), used for ranges whose isqrt(B) exceeds four
- *              times the bound.
+ *              2^(seg_log2 + 4).
  *   bucket_mib HBM budget for the strike bitmaps of one round, in MiB
  *              (0 = 512); larger batches run in several rounds.
  */
@@ -166,7 +165,7 @@ gb_status gb_get_params(gb_params *p);
 
 /*
  * Autotuner: time a calibration run of [A, B] (at most 2^36 evens) under each
- * segment size, workgroup size and probe window (and, when isqrt(B) > 2^19,
+ * segment size, workgroup size and probe window (and, when isqrt(B) > 2^22,
  * with and without bucket lists), keep the fastest as the current parameters
  * and write it to *best (may be NULL).  Results of later calls do not depend
  * on the choice.

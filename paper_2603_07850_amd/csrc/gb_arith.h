@@ -33,15 +33,20 @@ __device__ __forceinline__ uint32_t gb_mod_small_quot(uint64_t y, uint32_t p, do
     return (uint32_t)t;
 }
 
-// x mod p for any 64-bit x and odd 3 <= p < 2^32.  The high word is reduced
-// first so that the second step's quotient fits 32 bits.
-__device__ __forceinline__ uint32_t gb_mod_u64_u32(uint64_t x, uint32_t p)
+// x mod p for any 64-bit x and odd 3 <= p < 2^32, given inv = gb_recip(p).
+// The high word is reduced first so that the second step's quotient fits 32
+// bits.
+__device__ __forceinline__ uint32_t gb_mod_u64_u32_inv(uint64_t x, uint32_t p, double inv)
 {
-    const double inv = gb_recip(p);
     uint32_t xh = (uint32_t)(x >> 32);
     if (xh >= p)
         xh = gb_mod_small_quot(xh, p, inv);
     return gb_mod_small_quot(((uint64_t)xh << 32) | (uint32_t)x, p, inv);
+}
+
+__device__ __forceinline__ uint32_t gb_mod_u64_u32(uint64_t x, uint32_t p)
+{
+    return gb_mod_u64_u32_inv(x, p, gb_recip(p));
 }
 
 // floor(sqrt(x)) exactly: a double estimate corrected with integer squares

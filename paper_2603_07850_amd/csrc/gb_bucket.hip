@@ -12,13 +12,12 @@
 // segment land on words spread over its window, so they do not queue on one
 // address.  The segment kernel folds its bitmap into the LDS window.
 //
-// Work is cut into items (prime, sub-range of the chunk): primes of the band
-// (2^b, 2^(b+1)] get sub-ranges of 8 * 2^b bits, so an item takes one
-// remainder and makes at most 16 strikes whatever the prime's size.  A tile
-// is one sub-range against kFillThreads * kFillPerThread consecutive primes.  Every
-// offset is relative to the chunk's window start and bounded by the chunk's
-// last odd number, so no absolute value beyond it is formed (the overflow
-// guards of the paper's Sec. 3.4).
+// Work is cut into items (prime, chunk): a task pairs the primes of one band
+// (2^b, 2^(b+1)] with a group of consecutive chunks, and a thread loads each
+// of its primes and its reciprocal once for the whole group.  Every offset is
+// relative to the chunk's window start and bounded by the chunk's last odd
+// number, so no absolute value beyond it is formed (the overflow guards of the
+// paper's Sec. 3.4).
 #include "gb_arith.h"
 #include "gb_internal.h"
 
@@ -41,49 +40,41 @@ __device__ void fill_tile(const GbBucketArgs &a, uint64_t tile)
             hi = mid - 1;
     }
     const GbFillTask T = a.task[lo];
-    const GbChunk C = a.chunk[T.chunk];
     const uint32_t E = 1u << a.log2e;
     const uint32_t emask = E - 1;
-    // tile -> (sub-range j, block of kFillThreads * kFillPerThread primes)
     constexpr uint32_t PB = kFillThreads * kFillPerThread;
-    const uint32_t pblocks = (T.np + PB - 1) / PB;
-    const uint64_t t = tile - T.tile_first;
-    const uint32_t j = (uint32_t)(t / pblocks);
-    const uint32_t pb = (uint32_t)(t - (uint64_t)j * pblocks);
-    const uint64_t b0 = (uint64_t)j << T.sl_log2;        // first bit of the sub-range
-    if (b0 > C.dmax)
-        return;
-    uint64_t b1 = b0 + (1ull << T.sl_log2) - 1;          // last bit of the sub-range
-    if (b1 > C.dmax)
-        b1 = C.dmax;
-    const uint64_t qs = C.Q0 + 2 * b0;                   // <= the chunk's last odd number
+    const uint32_t pb = (uint32_t)(tile - T.tile_first);
     for (uint32_t m = 0; m < kFillPerThread; ++m) {
         const uint32_t pi = pb * PB + threadIdx.x + m * kFillThreads;
         if (pi >= T.np)
             break;
         const uint64_t idx = (uint64_t)T.p_first + pi;
-        if (idx >= C.p_root)
-            break;
         const uint32_t p = a.primes[idx];
-        // first odd multiple of p at or above max(Q0 + 2*b0, p^2), as a window bit
-        const uint32_t r = gb_mod_u64_u32(qs, p);
-        uint64_t x = r ? p - r : 0;
-        if (x & 1)
-            x += p;                                          // qs is odd: x must be even
-        uint64_t d = b0 + (x >> 1);
+        const double inv = gb_recip(p);
         const uint64_t p2 = (uint64_t)p * p;
-        if (p2 > C.Q0) {
-            const uint64_t dsq = (p2 - C.Q0) >> 1;
-            if (dsq > d)
-                d = dsq;
-        }
-        for (; d <= b1; d += p) {
-            const uint64_t s = d >> a.log2e;
-            const uint32_t off = (uint32_t)d & emask;
-            if (s < C.nseg)
-                strike(a, C.seg_first + s, off);
-            if (off < a.H && s >= 1 && s - 1 < C.nseg)
-                strike(a, C.seg_first + s - 1, off + E);
+        for (uint32_t cc = 0; cc < T.nchunk; ++cc) {
+            const GbChunk &C = a.chunk[T.chunk_first + cc];
+            if (idx >= C.p_root)
+                continue;
+            // first odd multiple of p at or above max(Q0, p^2), as a window bit
+            const uint32_t r = gb_mod_u64_u32_inv(C.Q0, p, inv);
+            uint64_t x = r ? p - r : 0;
+            if (x & 1)
+                x += p;                                          // Q0 is odd: x must be even
+            uint64_t d = x >> 1;
+            if (p2 > C.Q0) {
+                const uint64_t dsq = (p2 - C.Q0) >> 1;
+                if (dsq > d)
+                    d = dsq;
+            }
+            for (; d <= C.dmax; d += p) {
+                const uint64_t s = d >> a.log2e;
+                const uint32_t off = (uint32_t)d & emask;
+                if (s < C.nseg)
+                    strike(a, C.seg_first + s, off);
+                if (off < a.H && s >= 1 && s - 1 < C.nseg)
+                    strike(a, C.seg_first + s - 1, off + E);
+            }
         }
     }
 }

@@ -96,16 +96,16 @@ struct GbChunk {
 };
 
 // One fill task: the table primes [p_first, p_first + np) of one band
-// (2^b, 2^(b+1)] against one chunk cut into nsub sub-ranges of 2^sl_log2 bits,
-// so that a work item (prime, sub-range) has one remainder and a few strikes.
+// (2^b, 2^(b+1)] against nchunk consecutive chunks of the round; a tile is
+// kFillThreads * kFillPerThread consecutive primes of the task, and each
+// (prime, chunk) item takes one remainder and walks the prime's multiples
+// across the chunk.
 struct GbFillTask {
     uint64_t tile_first;  // first fill tile of the task (within the round)
-    uint32_t chunk;       // index into the round's chunks
+    uint32_t chunk_first; // index into the round's chunks
+    uint32_t nchunk;
     uint32_t p_first;
-    uint32_t np;          // an upper bound; items past the chunk's p_root exit
-    uint32_t nsub;
-    uint32_t sl_log2;
-    uint32_t pad;
+    uint32_t np;          // an upper bound; items past a chunk's p_root skip it
 };
 
 struct GbBucketArgs {
@@ -147,7 +147,7 @@ hipError_t gb_probe_occupancy(int seg_log2, int wg_size, int *blocks_per_cu);
 
 constexpr uint32_t kFillThreads = 256;
 constexpr uint32_t kFillPerThread = 4;   // work items per thread in one fill tile
-constexpr uint32_t kFillStrikes = 8;     // sub-range = kFillStrikes * 2^b bits for band b
+constexpr uint32_t kFillChunks = 16;     // chunks of one fill task
 hipError_t gb_launch_bucket_reset(uint32_t *bitmap, uint64_t words, hipStream_t s);
 hipError_t gb_launch_bucket_fill(const GbBucketArgs &a, uint32_t grid, hipStream_t s);
 

@@ -387,15 +387,6 @@ struct Plan {
 // pi(x) < 1.25506 x / ln x for x > 1 (Rosser and Schoenfeld 1962).
 uint64_t pi_upper(uint64_t x) { return (uint64_t)(1.25506 * (double)x / std::log((double)x)) + 16; }
 
-// Expected strikes of the primes in (lb, root] on a window of `bits` odd
-// numbers: bits * sum 1/p ~ bits * ln(ln root / ln lb) (Mertens).
-double expected_strikes(double bits, double lb, double root)
-{
-    if (root <= lb)
-        return 0.0;
-    return bits * std::log(std::log(root) / std::log(lb));
-}
-
 gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, const gb_params &pr,
                     Plan &pl)
 {
@@ -418,7 +409,7 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
     const uint64_t E = 1ull << lg;
     const uint64_t Wbits = E + pl.H;
     // bucket bound: a prime above it strikes a window at most once or twice
-    uint32_t blog = pr.bucket_log2 ? pr.bucket_log2 : lg + 1;
+    uint32_t blog = pr.bucket_log2 ? pr.bucket_log2 : lg + 4;
     if (blog > 32)
         blog = 32;
     pl.lb = blog >= 32 ? 0xFFFFFFFFull : (1ull << blog);
@@ -429,7 +420,7 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
     pl.iv.resize(k);
     pl.An.resize(k);
     pl.Bn.resize(k);
-    std::vector<double> hits(k, 0.0);   // > 0: the interval needs primes above the bound
+    std::vector<uint8_t> usebm(k, 0);   // the interval takes strike bitmaps
     std::vector<uint64_t> order;
     order.reserve(k);
     uint64_t evens = 0;
@@ -450,21 +441,25 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
             }
             g.nE = (b - a) / 2 + 1;
             g.nseg = (g.nE + E - 1) >> lg;
-            // automatic bound: strike bitmaps only pay when the root is well
-            // above the bound (for [4, 10^12] the per-segment remainders of the
-            // primes up to 10^6 are cheaper than filling bitmaps)
-            const uint64_t need = pr.bucket_log2 ? pl.lb : 4 * pl.lb;
-            if (root > need && a > 2 * (uint64_t)pl.H + 2)
-                hits[i] = expected_strikes((double)Wbits, (double)pl.lb, (double)root);
+            // bitmaps only for intervals whose root is above the bound (the
+            // automatic bound 2^(seg_log2+4) keeps all of [4, 10^12] in the
+            // per-segment tiers)
+            if (root > pl.lb && a > 2 * (uint64_t)pl.H + 2)
+                usebm[i] = 1;
         }
         evens += g.nE;
         pl.iv[i] = g;
         order.push_back(i);
     }
-    // segments are numbered interval by interval; intervals without bucket
-    // work come first, then the others by growing top
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint64_t x, uint64_t y) { return hits[x] < hits[y]; });
+    // segments are numbered interval by interval; intervals without bitmaps
+    // come first, then the others by growing top (so that the chunks of a
+    // round come by growing root, mostly, and a fill task's chunk group needs
+    // about the same primes)
+    std::stable_sort(order.begin(), order.end(), [&](uint64_t x, uint64_t y) {
+        if (usebm[x] != usebm[y])
+            return usebm[x] < usebm[y];
+        return usebm[x] && pl.Bn[x] < pl.Bn[y];
+    });
     uint64_t seg = 0;
     for (uint64_t i : order) {
         pl.iv[i].seg_first = seg;
@@ -480,7 +475,7 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
     {
         Round r;
         r.seg_base = 0;
-        while (oi < order.size() && hits[order[oi]] == 0.0) {
+        while (oi < order.size() && !usebm[order[oi]]) {
             r.nsegs += pl.iv[order[oi]].nseg;
             ++oi;
         }
@@ -490,8 +485,36 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
     }
     Round cur;
     cur.seg_base = pos;
+    std::vector<uint64_t> croot;   // isqrt of each chunk's top (host side)
+    const uint64_t per_tile = (uint64_t)kFillThreads * kFillPerThread;
     auto close_round = [&]() {
         if (cur.nsegs) {
+            // fill tasks: per prime band (2^b, 2^(b+1)] and group of
+            // kFillChunks consecutive chunks of the round that reach the band
+            for (uint32_t bb = blog; bb < 32; ++bb) {
+                const uint64_t pf = c.pi2[bb];
+                for (uint64_t g0 = 0; g0 < cur.nchunk; g0 += kFillChunks) {
+                    const uint64_t g1 = std::min<uint64_t>(g0 + kFillChunks, cur.nchunk);
+                    uint64_t rmax = 0;
+                    for (uint64_t q = g0; q < g1; ++q)
+                        rmax = std::max(rmax, croot[cur.chunk_first + q]);
+                    if (rmax <= (1ull << bb))
+                        continue;
+                    const uint64_t pe = std::min<uint64_t>(
+                        c.pi2[bb + 1], std::min<uint64_t>(pi_upper(rmax), c.nprimes));
+                    if (pe <= pf)
+                        continue;
+                    GbFillTask t = {};
+                    t.tile_first = cur.ntiles;
+                    t.chunk_first = (uint32_t)g0;
+                    t.nchunk = (uint32_t)(g1 - g0);
+                    t.p_first = (uint32_t)pf;
+                    t.np = (uint32_t)(pe - pf);
+                    cur.ntiles += (t.np + per_tile - 1) / per_tile;
+                    pl.tasks.push_back(t);
+                    ++cur.ntask;
+                }
+            }
             pl.rounds.push_back(cur);
             pl.max_round_segs = std::max(pl.max_round_segs, cur.nsegs);
             pl.max_bitmap_words = std::max(pl.max_bitmap_words, cur.nsegs * (uint64_t)pl.words);
@@ -503,7 +526,6 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
     };
     cur.chunk_first = pl.chunks.size();
     cur.task_first = pl.tasks.size();
-    const uint64_t per_tile = (uint64_t)kFillThreads * kFillPerThread;
     for (; oi < order.size(); ++oi) {
         const uint64_t i = order[oi];
         const GbInterval &I = pl.iv[i];
@@ -527,43 +549,15 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
             ch.Q0 = n0 - 1 - 2ull * pl.H;                         // n0 > 2H + 2 here
             ch.dmax = (top - ch.Q0) / 2;
             ch.p_root = 0;                                        // set on the device
-            const uint64_t root = isqrt_u64(top);
-            const uint64_t pub = std::min<uint64_t>(pi_upper(root), c.nprimes);
-            // one task per prime band (2^b, 2^(b+1)] that reaches below the root
-            std::vector<GbFillTask> ts;
-            uint64_t tiles = 0;
-            for (uint32_t bb = blog; bb < 32 && (1ull << bb) < root; ++bb) {
-                const uint64_t pf = c.pi2[bb];
-                const uint64_t pe = std::min<uint64_t>(c.pi2[bb + 1], pub);
-                if (pe <= pf)
-                    continue;
-                GbFillTask t = {};
-                t.p_first = (uint32_t)pf;
-                t.np = (uint32_t)(pe - pf);
-                t.sl_log2 = bb + 3;   // kFillStrikes * 2^b bits
-                t.nsub = (uint32_t)(((ch.dmax + 1) + (1ull << t.sl_log2) - 1) >> t.sl_log2);
-                t.tile_first = tiles;
-                tiles += (uint64_t)t.nsub * ((t.np + per_tile - 1) / per_tile);
-                ts.push_back(t);
-            }
-
-            if (cur.nsegs && ((cur.nsegs + ns) * (uint64_t)pl.words * 4 > budget ||
-                              cur.ntiles + tiles > (1ull << 40)))
+            if (cur.nsegs && (cur.nsegs + ns) * (uint64_t)pl.words * 4 > budget)
                 close_round();
             cur.bm = 1;
             ch.seg_first = I.seg_first + s0;
-            const uint32_t cidx = (uint32_t)(pl.chunks.size() - cur.chunk_first);
-            for (GbFillTask &t : ts) {
-                t.chunk = cidx;
-                t.tile_first += cur.ntiles;
-                pl.tasks.push_back(t);
-                ++cur.ntask;
-            }
-            cur.ntiles += tiles;
             cur.nsegs += ns;
             pos += ns;
             ++cur.nchunk;
             pl.chunks.push_back(ch);
+            croot.push_back(isqrt_u64(top));
         }
     }
     close_round();
@@ -980,8 +974,9 @@ gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream, gb_p
     const uint32_t logs[3] = {18, 19, 20};
     const uint32_t wgs[3] = {256, 512, 1024};
     const uint32_t wins[2] = {4096, 16384};
-    // the bucket bound matters only when the range reaches primes above 2^19
-    const bool big = isqrt_u64(Bn) > (1ull << 19);
+    // the bucket bound matters only when the range reaches primes above the
+    // smallest automatic bound, 2^22
+    const bool big = isqrt_u64(Bn) > (1ull << 22);
     const uint32_t blogs[2] = {0, 32};
     const int nb = big ? 2 : 1;
     double best_t = 1e300;

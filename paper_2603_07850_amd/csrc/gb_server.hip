@@ -235,7 +235,7 @@ gb_status gb_server_open(const gb_server_config *cfg, gb_server **out)
     gb_server *s = new gb_server();
     s->cfg = *cfg;
     s->seg_evens = 1ull << p.seg_log2;
-    s->lb_log2 = p.bucket_log2 ? p.bucket_log2 : p.seg_log2 + 1;
+    s->lb_log2 = p.bucket_log2 ? p.bucket_log2 : p.seg_log2 + 4;
     s->t_open = Clock::now();
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
