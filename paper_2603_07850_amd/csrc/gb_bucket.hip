@@ -23,10 +23,14 @@
 
 namespace {
 
+// Set window bit off of segment g in its strike bitmap, stored by class like
+// the LDS window: bit off / 3 of class array off mod 3.
 __device__ __forceinline__ void strike(const GbBucketArgs &a, uint64_t g, uint32_t off)
 {
     const uint64_t rel = g - a.seg_base;
-    atomicOr(&a.bitmap[rel * a.words + (off >> 5)], 1u << (off & 31));
+    const uint32_t i = __umulhi(off, 0xAAAAAAABu) >> 1;  // off / 3
+    const uint32_t t = off - 3 * i;
+    atomicOr(&a.bitmap[rel * a.words + t * a.wcu + (i >> 5)], 1u << (i & 31));
 }
 
 __device__ void fill_tile(const GbBucketArgs &a, uint64_t tile)
@@ -52,6 +56,7 @@ __device__ void fill_tile(const GbBucketArgs &a, uint64_t tile)
         const uint32_t p = a.primes[idx];
         const double inv = gb_recip(p);
         const uint64_t p2 = (uint64_t)p * p;
+        const uint32_t pm3 = p % 3;
         for (uint32_t cc = 0; cc < T.nchunk; ++cc) {
             const GbChunk &C = a.chunk[T.chunk_first + cc];
             if (idx >= C.p_root)
@@ -67,13 +72,21 @@ __device__ void fill_tile(const GbBucketArgs &a, uint64_t tile)
                 if (dsq > d)
                     d = dsq;
             }
+            // the odd number Q0 + 2d is a multiple of 3 when d = Q0 (mod 3):
+            // the window keeps those bits clear, so they are not struck
+            const uint32_t q0m3 = (uint32_t)(C.Q0 % 3);
+            uint32_t dm3 = (uint32_t)(d % 3);
             for (; d <= C.dmax; d += p) {
-                const uint64_t s = d >> a.log2e;
-                const uint32_t off = (uint32_t)d & emask;
-                if (s < C.nseg)
-                    strike(a, C.seg_first + s, off);
-                if (off < a.H && s >= 1 && s - 1 < C.nseg)
-                    strike(a, C.seg_first + s - 1, off + E);
+                if (dm3 != q0m3) {
+                    const uint64_t s = d >> a.log2e;
+                    const uint32_t off = (uint32_t)d & emask;
+                    if (s < C.nseg)
+                        strike(a, C.seg_first + s, off);
+                    if (off < a.H && s >= 1 && s - 1 < C.nseg)
+                        strike(a, C.seg_first + s - 1, off + E);
+                }
+                dm3 += pm3;
+                dm3 = dm3 >= 3 ? dm3 - 3 : dm3;
             }
         }
     }

@@ -77,13 +77,34 @@ struct GbProbeArgs {
     GbIvDone *done;
     const uint32_t *bitmap;   // per segment (E + H)/32 words: bits struck by large
                               // primes; null when the launch has no buckets
-    const uint32_t *ctab;     // probe candidate table, 3 words per candidate
+    const uint32_t *ctab;     // probe candidate tables, 3 words per entry (see below)
+    const uint32_t *ptab;     // the candidate p of each table entry
+    uint32_t wcu;             // class-array words in use per segment, (E + H)/96 + 1
+    uint32_t nv[9];           // entries of table (r, t3) with p <= the probe window
 };
 
-// Probe candidate table: for the odd primes p_k <= 65536 (k = 1, 2, ...),
-// entry k - 1 holds {4 * ceil((p_k >> 1) / 32), (-(p_k >> 1)) mod 32,
-// p_k - p_(k-1) with p_0 = 0}; kCandPad zero entries follow the last one.
-constexpr uint32_t kCandPad = 16;
+// The segment window in LDS is stored by class: odd bit b (odd number
+// q_lo + 2b) is bit b / 3 of class array b mod 3.  One class holds the
+// multiples of 3 (the class t3 with q_lo + 2*t3 = 0 mod 3); the other two hold
+// everything else.  The halo H is a multiple of 96, so class index
+// b / 3 = i' + H/3 + (r - h - t)/3 for b = r + 3i' + H - h.
+constexpr uint32_t kHaloMax = 32832;  // largest halo: multiple of 96 >= 32767 + 2
+
+// Words of one class array in the LDS window of a 2^log2e-even segment (with
+// room for the probe's reads past the last block).
+constexpr uint32_t gb_class_words(int log2e)
+{
+    return (uint32_t)(((1u << log2e) + kHaloMax + 95) / 96) + 4;
+}
+
+// Probe candidate tables, one per (segment size 2^18 / 2^19 / 2^20, class r of
+// the evens, class t3 of the multiples of 3): the odd primes p <= 65536 whose
+// n - p avoids class t3 (the others cannot be prime, n - p = 3 aside), in
+// ascending order.  Entry: {byte offset, to subtract from the lane's base,
+// of the first LDS word holding bit(n - p); funnel-shift amount; p minus the
+// previous entry's p (0 before the first)}.  Table (lg, r, t3) starts at entry
+// ((lg - 18) * 9 + r * 3 + t3) * kCandStride.
+constexpr uint32_t kCandStride = 6560;
 
 // A run of consecutive segments of one interval that the bucket-fill kernel
 // treats as one window [Q0, Q0 + 2*dmax] of odd numbers.
@@ -115,10 +136,11 @@ struct GbBucketArgs {
     uint32_t ntask;
     uint32_t log2e;
     uint32_t H;
-    uint32_t words;       // bitmap words per segment, (E + H)/32
+    uint32_t words;       // bitmap words per segment, 3 * wcu
     uint64_t ntiles;
     uint64_t seg_base;    // global index of the round's first segment
     uint32_t *bitmap;     // the round's strike bitmaps, segment after segment
+    uint32_t wcu;         // class-array words per segment bitmap (three per segment)
 };
 
 // Set the calling thread's gb_last_error() message (host code).

@@ -117,7 +117,7 @@ struct Ctx {
     uint64_t T = 0;
     uint64_t nprimes = 0;
     DevBuf primes;
-    DevBuf d_ctab;                // probe candidate table (gb_internal.h)
+    DevBuf d_ctab, d_ptab;        // probe candidate tables and their p (gb_internal.h)
     std::vector<uint32_t> small;  // host copy of the primes <= 65536 (launch planning)
     gb_params params = {18, 256, 4096, 0, 0, 0};
     uint64_t pi2[33] = {};        // number of table primes <= 2^k
@@ -206,6 +206,7 @@ void release_all(Ctx &c)
 {
     c.primes.release();
     c.d_ctab.release();
+    c.d_ptab.release();
     c.d_iv.release();
     c.d_rec.release();
     c.d_spill.release();
@@ -325,20 +326,42 @@ gb_status build_table(Ctx &c, uint64_t limit)
         release_all(c);
         return GB_EHIP;
     }
-    // probe candidate table from the odd primes <= 65536
-    std::vector<uint32_t> tab(((size_t)nsmall - 1 + kCandPad) * 3, 0u);
-    for (size_t k = 1; k < nsmall; ++k) {
-        const uint32_t pk = c.small[k], h = pk >> 1;
-        uint32_t *t = &tab[(k - 1) * 3];
-        t[0] = ((h + 31) >> 5) << 2;
-        t[1] = (0u - h) & 31;
-        t[2] = pk - (k > 1 ? c.small[k - 1] : 0u);
+    // probe candidate tables from the odd primes <= 65536, one per (segment
+    // size, class r of the evens, class t3 of the multiples of 3)
+    std::vector<uint32_t> tab((size_t)27 * kCandStride * 3, 0u), ptab((size_t)27 * kCandStride, 0u);
+    for (int lg = 18; lg <= 20; ++lg) {
+        const int64_t WC = gb_class_words(lg);
+        for (int64_t r = 0; r < 3; ++r)
+            for (int64_t t3 = 0; t3 < 3; ++t3) {
+                const size_t base = ((size_t)(lg - 18) * 9 + (size_t)(r * 3 + t3)) * kCandStride;
+                size_t e_ = 0;
+                uint32_t prev = 0;
+                for (size_t k = 1; k < nsmall; ++k) {
+                    const uint32_t pk = c.small[k];
+                    const int64_t h = pk >> 1;
+                    const int64_t t = (((r - h) % 3) + 3) % 3;
+                    if (t == t3)
+                        continue;
+                    const int64_t d = (r - h - t) / 3;                   // exact
+                    const int64_t fw = d >= 0 ? d / 32 : -((-d + 31) / 32);  // floor(d / 32)
+                    uint32_t *te = &tab[(base + e_) * 3];
+                    te[0] = (uint32_t)(-4 * (t * WC + fw));
+                    te[1] = (uint32_t)(d - 32 * fw);
+                    te[2] = pk - prev;
+                    ptab[base + e_] = pk;
+                    prev = pk;
+                    ++e_;
+                }
+            }
     }
-    if ((st = c.d_ctab.reserve(tab.size() * 4)) != GB_OK) {
+    if ((st = c.d_ctab.reserve(tab.size() * 4)) != GB_OK ||
+        (st = c.d_ptab.reserve(ptab.size() * 4)) != GB_OK) {
         release_all(c);
         return st;
     }
     e = hipMemcpy(c.d_ctab.p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c.d_ptab.p, ptab.data(), ptab.size() * 4, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         set_err("candidate table upload failed: %s", hipGetErrorString(e));
         release_all(c);
@@ -381,7 +404,9 @@ struct Plan {
     std::vector<GbFillTask> tasks;
     uint64_t max_round_segs = 0;
     uint64_t max_bitmap_words = 0;
-    uint32_t words = 0;       // window words per segment, (E + H)/32
+    uint32_t wcu = 0;         // class-array words per segment, (E + H)/96 + 1
+    uint32_t words = 0;       // strike-bitmap words per segment, 3 * wcu
+    uint32_t nv[9] = {};      // probe table entries per (r, t3) within the window
 };
 
 // pi(x) < 1.25506 x / ln x for x > 1 (Rosser and Schoenfeld 1962).
@@ -404,7 +429,18 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
     const uint64_t nc = small_count_le(c, pwin);  // includes 2
     pl.ncand = (uint32_t)(nc > 0 ? nc - 1 : 0);
     uint32_t hmax = pl.ncand ? (c.small[pl.ncand] - 1) / 2 : 0;
-    pl.H = std::max<uint32_t>(32, (hmax + 31) & ~31u);
+    // halo: a multiple of 96 (32-bit words of the three class arrays) reaching
+    // two bits past the largest candidate's offset
+    pl.H = std::max<uint32_t>(96, (hmax + 2 + 95) / 96 * 96);
+    for (uint32_t k = 1; k <= pl.ncand; ++k) {
+        const int64_t h = c.small[k] >> 1;
+        for (int64_t r = 0; r < 3; ++r) {
+            const int64_t t = (((r - h) % 3) + 3) % 3;
+            for (int64_t t3 = 0; t3 < 3; ++t3)
+                if (t != t3)
+                    ++pl.nv[r * 3 + t3];
+        }
+    }
     const uint32_t lg = pr.seg_log2;
     const uint64_t E = 1ull << lg;
     const uint64_t Wbits = E + pl.H;
@@ -415,7 +451,8 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
     pl.lb = blog >= 32 ? 0xFFFFFFFFull : (1ull << blog);
     pl.lb_count = (uint32_t)std::min<uint64_t>(blog >= 32 ? c.nprimes : c.pi2[blog], c.nprimes);
     const uint64_t budget = (uint64_t)(pr.bucket_mib ? pr.bucket_mib : 512) << 20;
-    pl.words = (uint32_t)(Wbits / 32);
+    pl.wcu = (uint32_t)((Wbits + 95) / 96 + 1);
+    pl.words = 3 * pl.wcu;
 
     pl.iv.resize(k);
     pl.An.resize(k);
@@ -603,6 +640,7 @@ gb_status enqueue_kernels(Ctx &c, const Plan &pl, uint64_t P_max, const gb_param
             b.log2e = pr.seg_log2;
             b.H = pl.H;
             b.words = pl.words;
+            b.wcu = pl.wcu;
             b.ntiles = r.ntiles;
             b.seg_base = r.seg_base;
             b.bitmap = (uint32_t *)c.d_bitmap.p;
@@ -627,6 +665,10 @@ gb_status enqueue_kernels(Ctx &c, const Plan &pl, uint64_t P_max, const gb_param
         a.done = (GbIvDone *)c.d_done.p;
         a.bitmap = r.bm ? (const uint32_t *)c.d_bitmap.p : nullptr;
         a.ctab = (const uint32_t *)c.d_ctab.p;
+        a.ptab = (const uint32_t *)c.d_ptab.p;
+        a.wcu = pl.wcu;
+        for (int q = 0; q < 9; ++q)
+            a.nv[q] = pl.nv[q];
         const uint32_t g = (uint32_t)std::min<uint64_t>(grid, r.nsegs);
         GB_HIP(gb_launch_probe((int)pr.seg_log2, (int)pr.wg_size, g, a, s));
     }
@@ -655,7 +697,7 @@ std::vector<uint64_t> graph_key(const Ctx &c, const Plan &pl, uint64_t P_max, co
                                 uint32_t grid)
 {
     std::vector<uint64_t> key = {
-        (uint64_t)c.primes.p, (uint64_t)c.d_ctab.p, (uint64_t)c.d_iv.p, (uint64_t)c.d_rec.p, (uint64_t)c.d_spill.p,
+        (uint64_t)c.primes.p, (uint64_t)c.d_ctab.p, (uint64_t)c.d_ptab.p, (uint64_t)c.d_iv.p, (uint64_t)c.d_rec.p, (uint64_t)c.d_spill.p,
         (uint64_t)c.d_unres.p, (uint64_t)c.d_res.p, (uint64_t)c.d_ctr.p, (uint64_t)c.d_done.p,
         (uint64_t)c.d_bitmap.p, (uint64_t)pl.words, (uint64_t)c.d_chunk.p,
         (uint64_t)c.d_claims.p, (uint64_t)c.d_task.p, pl.chunks.size(), c.nprimes, pl.iv.size(),

@@ -95,13 +95,14 @@ namespace {
 
 // HBM reserved by a request while it is active: the strike bitmaps of one of
 // its pieces when its range reaches primes above the bucket bound (a window
-// of E + H <= E + 32768 bits per segment), plus its segment records.
+// of E + H <= E + 32832 bits per segment, in three class arrays), plus its
+// segment records.
 uint64_t reservation(const gb_server *s, const Req *r)
 {
     const uint64_t segs = std::min<uint64_t>((r->nE + s->seg_evens - 1) / s->seg_evens,
                                              s->cfg.piece_segments);
     const bool big = std::sqrt((double)r->Bn) > std::ldexp(1.0, (int)s->lb_log2);
-    return (big ? segs * ((s->seg_evens + 32768) / 8) : 0) + segs * 64 + 4096;
+    return (big ? segs * ((s->seg_evens + 32832) / 8 + 32) : 0) + segs * 64 + 4096;
 }
 
 void finish(gb_server *s, Req *r, Clock::time_point now)

@@ -40,7 +40,6 @@
 namespace {
 
 constexpr uint32_t kPre[10] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
-constexpr uint32_t kHaloMax = 32768;  // largest halo: candidates up to 65536
 constexpr uint32_t kFirstStrided = 11;  // primes[11] == 37
 constexpr uint32_t kPrimesInFlight = 8;  // thread-tier table loads issued together
 
@@ -99,6 +98,18 @@ __host__ __device__ constexpr uint32_t word_pattern(uint32_t p)
         m |= 1u << b;
     return m;
 }
+
+// 6^-1 mod p for p = 5..31 (6 * inv = 1 mod p).
+__host__ __device__ constexpr uint32_t inv6_mod(uint32_t p)
+{
+    uint32_t x = 1;
+    while ((6 * x) % p != 1)
+        ++x;
+    return x;
+}
+
+constexpr uint32_t kInv6[9] = {inv6_mod(5),  inv6_mod(7),  inv6_mod(11), inv6_mod(13), inv6_mod(17),
+                               inv6_mod(19), inv6_mod(23), inv6_mod(29), inv6_mod(31)};
 
 // Smallest bit index j of the window whose odd number q_lo + 2j is a multiple
 // of p and at least p^2 (saturated to 2^32 - 1).  The window start is q_lo
@@ -168,14 +179,33 @@ __device__ __forceinline__ uint32_t count_le(const uint32_t *primes, uint64_t np
     return (uint32_t)lo;
 }
 
-// Clear the window bits j, j + p, ... below weff (one prime, one thread).
-__device__ __forceinline__ void strike_prime(uint32_t *bits, uint32_t weff, uint32_t p, uint32_t j)
+// Clear the odd bits j, j + p, ... below weff (one prime, one thread) in the
+// class arrays of the window; bits of class t3 (multiples of 3) stay zero.  A
+// prime below the window strikes many bits: its multiples in each of the two
+// other classes t are the class indices i_t, i_t + p, ..., so each class gets
+// a plain strided loop.  A larger prime strikes at most once.
+template <uint32_t WC>
+__device__ __forceinline__ void strike_prime(uint32_t *bits, uint32_t weff, uint32_t t3, uint32_t p,
+                                             uint32_t j)
 {
+    if (j >= weff)
+        return;
     if (p < weff) {
-        for (uint32_t jj = j; jj < weff; jj += p)
-            atomicAnd(&bits[jj >> 5], ~(1u << (jj & 31)));
-    } else if (j < weff) {
-        atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
+        const uint32_t jm = j % 3, pm = p % 3;
+        for (uint32_t s2 = 1; s2 <= 2; ++s2) {
+            const uint32_t t = (t3 + s2) % 3;
+            const uint32_t kt = ((t + 3 - jm) * pm) % 3;  // j + kt*p = t (mod 3)
+            const uint32_t bt = j + kt * p;
+            uint32_t *cw = bits + t * WC;
+            const uint32_t lim = (weff + 2 - t) / 3;       // class indices in the window
+            for (uint32_t i = (bt - t) / 3; i < lim; i += p)
+                atomicAnd(&cw[i >> 5], ~(1u << (i & 31)));
+        }
+    } else {
+        const uint32_t i = __umulhi(j, 0xAAAAAAABu) >> 1;  // j / 3
+        const uint32_t t = j - 3 * i;
+        if (t != t3)
+            atomicAnd(&bits[__umul24(t, WC) + (i >> 5)], ~(1u << (i & 31)));
     }
 }
 
@@ -224,11 +254,11 @@ __global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_probe_kernel(GbProbeArgs a)
 {
     constexpr uint64_t E = 1ull << LOG2E;
-    constexpr uint32_t NW = (uint32_t)((E + kHaloMax) / 32);
+    constexpr uint32_t WC = gb_class_words(LOG2E);  // words per class array
     constexpr uint32_t NWAVE = NT / 64;
     // primes up to this bound strike a window >= 1024 times: one wave each
     constexpr uint32_t kWaveTierMax = (uint32_t)(E >> 9);
-    __shared__ uint32_t bits[NW];
+    __shared__ uint32_t bits[3 * WC];
     __shared__ unsigned long long sh_seg;
     __shared__ uint32_t sh_nroot;
     __shared__ unsigned long long red_sum[NWAVE];
@@ -239,13 +269,15 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63;
     const uint32_t wave = tid >> 6;
-    const uint32_t H = a.H;
-    const uint32_t H32 = H >> 5;
-    const uint32_t NWr = (uint32_t)((E + H) >> 5);  // window words in use
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(wave);
+    const uint32_t H = a.H;        // multiple of 96
+    const uint32_t H96 = H / 96;   // class-array words below a lane's first block word
+    const uint32_t WCU = a.wcu;    // class-array words in use
     const uint32_t *__restrict__ primes = a.primes;
     const cprime_t cp = (cprime_t)primes;
     // primes[kFirstStrided .. nwave) are cleared one prime per wave
     const uint32_t nwave = count_le(primes, a.nprimes, kWaveTierMax);
+    const uint32_t tabbase = (uint32_t)(LOG2E - 18) * 9;
 
     for (;;) {
         if (tid == 0)
@@ -271,11 +303,14 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
         const uint64_t n0 = I.A + 2 * E * js;
         const uint64_t rem = I.nE - E * js;
         const uint32_t cnt = (uint32_t)(rem < E ? rem : E);
-        const uint32_t weff = cnt - 1 + H;          // bits [0, weff) are read by the probe
+        const uint32_t weff = cnt - 1 + H;          // odd bits [0, weff) are read by the probe
         const bool neg = n0 <= 2ull * H;            // q_lo < 0
         const uint64_t qlo = n0 - 1 - 2ull * H;     // valid when !neg
         const uint64_t qneg = 2ull * H + 1 - n0;    // valid when neg
         const uint64_t qhi = n0 + 2ull * cnt - 5;   // largest q any n of the segment needs
+        // class of the multiples of 3: q_lo + 2*t3 = 0 (mod 3)
+        const uint32_t x3 = neg ? (uint32_t)(qneg % 3) : (uint32_t)((3 - qlo % 3) % 3);
+        const uint32_t t3 = (2 * x3) % 3;
         // windows starting in (0, 2^52) take the double-precision first-bit path
         const bool small = !neg && qlo < (1ull << 52);
         const double qd = (double)qlo;
@@ -286,69 +321,94 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                 sh_nroot = c;
         }
 
-        // ---- presieve: periodic masks of 3..31 ----
+        // ---- presieve: class t3 is all multiples of 3; periodic masks of 5..31 ----
         {
-            uint32_t ph[10];
-            uint32_t dec[10];
-#pragma unroll
-            for (int i = 0; i < 10; ++i) {
-                const uint32_t p = kPre[i];
-                const uint32_t x = neg ? (uint32_t)(qneg % p) : (uint32_t)((p - qlo % p) % p);
-                const uint32_t beta = (x & 1) ? (x + p) >> 1 : x >> 1;
-                ph[i] = (beta + p - (32u * tid) % p) % p;   // (beta - 32w) mod p at w = tid
-                dec[i] = (32u * NT) % p;
-            }
-            // bits struck by the primes above the bucket bound (if any)
             const uint32_t *__restrict__ bm =
-                a.bitmap ? a.bitmap + (seg - a.seg_base) * (uint64_t)NWr : nullptr;
-            for (uint32_t w = tid; w < NWr; w += NT) {
-                uint32_t m = bm ? bm[w] : 0u;
+                a.bitmap ? a.bitmap + (seg - a.seg_base) * (uint64_t)(3 * WCU) : nullptr;
+            uint32_t xr[9];   // -q_lo mod p (qneg mod p when neg) for p = 5..31
 #pragma unroll
-                for (int i = 0; i < 10; ++i) {
-                    m |= word_pattern(kPre[i]) << ph[i];
-                    ph[i] = ph[i] >= dec[i] ? ph[i] - dec[i] : ph[i] + kPre[i] - dec[i];
+            for (int i = 0; i < 9; ++i) {
+                const uint32_t p = kPre[i + 1];
+                xr[i] = neg ? (uint32_t)(qneg % p) : (uint32_t)((p - qlo % p) % p);
+            }
+            for (uint32_t t = 0; t < 3; ++t) {
+                uint32_t *cw = bits + t * WC;
+                if (t == t3) {
+                    for (uint32_t w = tid; w < WCU; w += NT)
+                        cw[w] = 0u;
+                    continue;
                 }
-                bits[w] = ~m;
+                // class index i is q = q_lo + 2t + 6i: a multiple of p when
+                // i = (xr - 2t) / 6 (mod p)
+                uint32_t ph[9];
+                uint32_t dec[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const uint32_t p = kPre[i + 1];
+                    const uint32_t phi = (((xr[i] + 2 * p - 2 * t) % p) * kInv6[i]) % p;
+                    ph[i] = (phi + p - (32u * tid) % p) % p;   // (phi - 32w) mod p at w = tid
+                    dec[i] = (32u * NT) % p;
+                }
+                const uint32_t *__restrict__ bmt = bm ? bm + t * WCU : nullptr;
+                for (uint32_t w = tid; w < WCU; w += NT) {
+                    uint32_t m = bmt ? bmt[w] : 0u;
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        m |= word_pattern(kPre[i + 1]) << ph[i];
+                        ph[i] = ph[i] >= dec[i] ? ph[i] - dec[i] : ph[i] + kPre[i + 1] - dec[i];
+                    }
+                    cw[w] = ~m;
+                }
             }
         }
         // restore the primes 3..31 and clear q <= 1 where the window reaches them
         if (neg || qlo <= 35) {
             __syncthreads();
-            const uint64_t bmax = neg ? (35 + qneg) >> 1 : (35 - qlo) >> 1;
-            for (uint64_t w = tid; w <= (bmax >> 5); w += NT) {
-                uint32_t v = bits[w];
-                for (uint32_t k = 0; k < 32; ++k) {
-                    const uint64_t b = 32 * w + k;
-                    if (b > bmax)
-                        break;
-                    const int64_t q = neg ? (int64_t)(2 * b) - (int64_t)qneg : (int64_t)(qlo + 2 * b);
-                    v = small_prime_35(q) ? (v | (1u << k)) : (v & ~(1u << k));
+            const uint64_t bmax = neg ? (35 + qneg) >> 1 : (35 - qlo) >> 1;  // odd bits 0..bmax
+            const uint32_t wmax = (uint32_t)((bmax / 3) >> 5);
+            for (uint32_t t = 0; t < 3; ++t) {
+                for (uint32_t w = tid; w <= wmax; w += NT) {
+                    uint32_t v = bits[t * WC + w];
+                    for (uint32_t k = 0; k < 32; ++k) {
+                        const uint64_t b = 3ull * (32 * w + k) + t;
+                        if (b > bmax)
+                            break;
+                        const int64_t q = neg ? (int64_t)(2 * b) - (int64_t)qneg : (int64_t)(qlo + 2 * b);
+                        v = small_prime_35(q) ? (v | (1u << k)) : (v & ~(1u << k));
+                    }
+                    bits[t * WC + w] = v;
                 }
-                bits[w] = v;
             }
         }
         __syncthreads();
 
         const uint32_t nroot = __builtin_amdgcn_readfirstlane(sh_nroot);  // published by the barrier above
         const uint32_t nsieve = nroot < a.lb_count ? nroot : a.lb_count;  // primes cleared here
-        const uint32_t wend = (weff + 31) >> 5;
 
         // ---- strided clears, one prime per wave: 37 <= p <= kWaveTierMax ----
-        // Lane l strikes bits j0 + l*p + m*64p; 64p is a multiple of 32, so a
-        // lane's bit position within its words, and its mask, never change.
+        // The prime's odd multiples b = j0 + kp fall in the two classes other
+        // than t3 at class indices i_t + mp.  Lane l strikes i_t + l*p + m*64p;
+        // 64p is a multiple of 32, so a lane's bit position and mask never change.
         {
-            const uint32_t wv = __builtin_amdgcn_readfirstlane(wave);
             const uint32_t wave_end = nwave < nsieve ? nwave : nsieve;
             for (uint32_t i = kFirstStrided + wv; i < wave_end; i += NWAVE) {
                 const uint32_t p = cp[i];
                 const uint32_t j0 = small ? first_bit_d(qd, (uint32_t)qlo, sq, p)
                                           : first_bit(qlo, qneg, neg, p);
-                const uint64_t jt = (uint64_t)j0 + (uint64_t)lane * p;
-                if (jt < weff) {
-                    const uint32_t mask = ~(1u << (jt & 31));
-                    const uint32_t step = 2 * p;  // words per 64p bits
-                    for (uint32_t w = (uint32_t)(jt >> 5); w < wend; w += step)
-                        atomicAnd(&bits[w], mask);
+                const uint32_t pm = p % 3, jm = j0 % 3;
+                for (uint32_t s2 = 1; s2 <= 2; ++s2) {
+                    const uint32_t t = (t3 + s2) % 3;
+                    const uint32_t kt = ((t + 3 - jm) * pm) % 3;   // j0 + kt*p = t (mod 3)
+                    const uint64_t bt = (uint64_t)j0 + (uint64_t)kt * p;
+                    const uint32_t lim = (weff + 2 - t) / 3;        // class indices in the window
+                    const uint64_t it = (bt - t) / 3 + (uint64_t)lane * p;
+                    if (bt < weff && it < lim) {
+                        const uint32_t mask = ~(1u << (it & 31));
+                        const uint32_t wend = (lim + 31) >> 5;
+                        uint32_t *cw = bits + t * WC;
+                        for (uint32_t w = (uint32_t)(it >> 5); w < wend; w += 2 * p)
+                            atomicAnd(&cw[w], mask);
+                    }
                 }
             }
         }
@@ -367,80 +427,107 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
 #pragma unroll
                     for (uint32_t t = 0; t < kPrimesInFlight; ++t)
                         if (pv[t])
-                            strike_prime(bits, weff, pv[t], first_bit_d(qd, (uint32_t)qlo, sq, pv[t]));
+                            strike_prime<WC>(bits, weff, t3, pv[t],
+                                             first_bit_d(qd, (uint32_t)qlo, sq, pv[t]));
                 } else {
 #pragma unroll
                     for (uint32_t t = 0; t < kPrimesInFlight; ++t)
                         if (pv[t])
-                            strike_prime(bits, weff, pv[t], first_bit(qlo, qneg, neg, pv[t]));
+                            strike_prime<WC>(bits, weff, t3, pv[t], first_bit(qlo, qneg, neg, pv[t]));
                 }
             }
         }
         __syncthreads();
 
         // ---- probe ----
-        // A lane owns a block of 64 consecutive evens, n0 + 128j + 2i for
-        // i < 64, as two mask words (lo: i < 32).  Candidate k (p = primes[k],
-        // k >= 1) comes from the candidate table as three words: the byte
-        // offset of the word holding bit(n - p) below the lane's first word,
-        // the funnel-shift amount and the gap p_k - p_(k-1) (p_0 = 0); four
-        // candidates make one 48-byte group, read with two scalar loads.  Per
-        // candidate a lane reads three LDS words, funnel-shifts the 64 bits
-        // n - p of its evens, counts its open evens and removes the hits.  The
-        // checksum of a block is accumulated in gap form: the sum of p_min
-        // over the evens resolved by candidates 1..K equals the sum over k of
-        // gap_k * (evens open before k), minus p_K per even still open after K.
-        const cgroup_t gt = (cgroup_t)a.ctab;
-        const ccand_t ct = (ccand_t)a.ctab;
-        const uint32_t ncand = a.ncand;
-        const uint32_t ngrp = ncand >> 2;
+        // The evens of the segment fall in three classes r (n = n0 + 2r + 6i',
+        // i' = 0, 1, ...).  A wave takes 64 blocks of one class; a lane owns a
+        // block of 64 consecutive i' as two mask words (lo: the first 32).  For
+        // an even of class r and candidate p, n - p lies in class
+        // t = (r - (p-1)/2) mod 3 of the window; candidates with t = t3 give a
+        // multiple of 3 and are absent from the class's table, so a block tests
+        // only the candidates that can hit.  Table entry k (p = its p) holds the
+        // byte offset of the LDS word with bit(n - p) below the lane's first
+        // word, the funnel-shift amount and the gap to the previous entry's p;
+        // four entries make one 48-byte group, read with two scalar loads.  Per
+        // entry a lane reads three LDS words, funnel-shifts the 64 bits n - p of
+        // its evens, counts its open evens and removes the hits.  The checksum
+        // of a block is accumulated in gap form: the sum of p_min over the evens
+        // resolved by entries 1..K equals the sum over k of gap_k * (evens open
+        // before k), minus p_K per even still open after K.
         const char *lds = (const char *)bits;
-        const uint32_t nblk = (cnt + 63) >> 6;
         uint64_t sum = 0;
         uint32_t nres = 0;
         uint32_t bestp = 0;
         uint64_t bestn = 0;
-        if (n0 == 4 && tid == 0) {  // 4 = 2 + 2, the only n whose p_min is even
-            sum = 2;
-            nres = 1;
-            bestp = 2;
-            bestn = 4;
+        // 4 = 2 + 2 (the only even p_min) and 6 = 3 + 3 (n - p = 3 lies in
+        // class t3) are set here; the probe skips them
+        const bool has6 = a.ncand >= 1 && (n0 == 6 || (n0 == 4 && cnt > 1));
+        if (tid == 0) {
+            if (n0 == 4) {
+                sum = 2;
+                nres = 1;
+                bestp = 2;
+                bestn = 4;
+            }
+            if (has6) {
+                sum += 3;
+                nres += 1;
+                bestp = 3;
+                bestn = 6;
+            }
         }
-        for (uint32_t jb = 0; jb < nblk; jb += NT) {
-            const uint32_t j = jb + tid;
-            const bool act = j < nblk;
+        uint32_t cntc[3], nblkc[3], nwbc[3];
+#pragma unroll
+        for (uint32_t r = 0; r < 3; ++r) {
+            cntc[r] = cnt > r ? (cnt - r + 2) / 3 : 0u;
+            nblkc[r] = (cntc[r] + 63) >> 6;
+            nwbc[r] = (nblkc[r] + 63) >> 6;
+        }
+        const uint32_t nwb = nwbc[0] + nwbc[1] + nwbc[2];
+        for (uint32_t wb = wv; wb < nwb; wb += NWAVE) {
+            const uint32_t r = wb < nwbc[0] ? 0u : (wb < nwbc[0] + nwbc[1] ? 1u : 2u);
+            const uint32_t wb0 = r == 0 ? 0u : (r == 1 ? nwbc[0] : nwbc[0] + nwbc[1]);
+            const uint32_t m = (wb - wb0) * 64 + lane;   // the lane's block in class r
+            const bool act = m < nblkc[r];
             uint32_t ul = 0, uh = 0;
             if (act) {
                 ul = 0xFFFFFFFFu;
                 uh = 0xFFFFFFFFu;
-                const uint32_t r = cnt & 63;
-                if (j == nblk - 1 && r) {
-                    if (r < 32) {
-                        ul = (1u << r) - 1;
+                const uint32_t left = cntc[r] - 64 * m;
+                if (left < 64) {
+                    if (left < 32) {
+                        ul = (1u << left) - 1;
                         uh = 0;
                     } else {
-                        uh = r == 32 ? 0u : (1u << (r - 32)) - 1;
+                        uh = left == 32 ? 0u : (1u << (left - 32)) - 1;
                     }
                 }
-                if (n0 == 4 && j == 0)
+                if (m == 0 && ((n0 == 4 && r == 0) || (has6 && r == (n0 == 4 ? 1u : 0u))))
                     ul &= ~1u;
             }
             const uint32_t open0 = (uint32_t)(__popc(ul) + __popc(uh));
-            const uint32_t base4 = ((act ? 2 * j : 0) + H32) * 4;  // byte address of the lane's first word
+            const uint32_t tab = tabbase + r * 3 + t3;
+            const cgroup_t gt = (cgroup_t)(a.ctab + (uint64_t)tab * 3 * kCandStride);
+            const ccand_t ct = (ccand_t)(a.ctab + (uint64_t)tab * 3 * kCandStride);
+            const cprime_t pt = (cprime_t)(a.ptab + (uint64_t)tab * kCandStride);
+            const uint32_t nv = a.nv[r * 3 + t3];
+            const uint32_t ngrp = nv >> 2;
+            const uint32_t base4 = ((act ? 2 * m : 0) + H96) * 4;  // byte address of the lane's first word
             uint32_t acc = 0;     // gap-form checksum, < 64 * 2^16 per block
-            uint32_t lastg = 0;   // first candidate of the last group with a hit
+            uint32_t lastg = 0;   // first entry of the last group with a hit
             uint32_t gl = 0;      // open evens at the start of that group
             uint32_t gh = 0;
-            uint32_t k = 1;       // next candidate
+            uint32_t k = 1;       // next entry (1-based)
             for (uint32_t g = 0; g < ngrp; ++g) {
                 probe_group(lds, base4, gt + g, k, ul, uh, acc, lastg, gl, gh);
                 k += 4;
                 if (__ballot((ul | uh) != 0) == 0)
                     break;
             }
-            // the candidates after the last full group, one at a time
+            // the entries after the last full group, one at a time
             if (__ballot((ul | uh) != 0) != 0) {
-                for (; k <= ncand; ++k) {
+                for (; k <= nv; ++k) {
                     const uint32_t sl = ul, sh = uh;
                     probe_one(lds, base4, ct[k - 1].off, ct[k - 1].sh, ct[k - 1].gap, ul, uh, acc);
                     const bool any = (ul != sl) | (uh != sh);
@@ -453,22 +540,23 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                     }
                 }
             }
-            // k - 1 is the last candidate the wave tested
+            // entry k - 1 is the last one the wave tested
             const uint32_t open = (uint32_t)(__popc(ul) + __popc(uh));
             if (open && k > 1)
-                acc -= cp[k - 1] * open;
+                acc -= pt[k - 2] * open;
             sum += acc;
             nres += open0 - open;
-            // Replay the last group with a hit: its last hitting candidate is
-            // the block's largest p_min, and the lowest bit of that hit is the
-            // smallest n attaining it.  Every candidate replayed here was also
+            // Replay the last group with a hit: its last hitting entry is the
+            // block's largest p_min, and the lowest bit of that hit is the
+            // smallest n attaining it.  Every entry replayed here was also
             // tested above, so the replay reproduces the same hits.
             if (lastg) {
                 uint32_t vl = gl, vh = gh, lastp = 0, hl = 0, hh = 0;
-                const uint32_t kend = lastg + 3 < ncand ? lastg + 3 : ncand;
-                const uint32_t *tab = a.ctab;
+                const uint32_t kend = lastg + 3 < nv ? lastg + 3 : nv;
+                const uint32_t *tabv = a.ctab + (uint64_t)tab * 3 * kCandStride;
+                const uint32_t *ptv = a.ptab + (uint64_t)tab * kCandStride;
                 for (uint32_t kk = lastg; kk <= kend && (vl | vh); ++kk) {
-                    const uint32_t *e = tab + 3 * (kk - 1);
+                    const uint32_t *e = tabv + 3 * (kk - 1);
                     const uint32_t addr = base4 - e[0];
                     const uint32_t w0 = *(const uint32_t *)(lds + addr);
                     const uint32_t w1 = *(const uint32_t *)(lds + addr + 4);
@@ -478,7 +566,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                     if (xl | xh) {
                         vl ^= xl;
                         vh ^= xh;
-                        lastp = primes[kk];
+                        lastp = ptv[kk - 1];
                         hl = xl;
                         hh = xh;
                     }
@@ -486,7 +574,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                 if (lastp > bestp) {
                     bestp = lastp;
                     const uint32_t bit = hl ? (uint32_t)(__ffs(hl) - 1) : 32u + (uint32_t)(__ffs(hh) - 1);
-                    bestn = n0 + 128ull * j + 2ull * bit;
+                    bestn = n0 + 2ull * r + 384ull * m + 6ull * bit;
                 }
             }
             while (ul | uh) {
@@ -500,7 +588,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                 }
                 const unsigned long long idx = atomicAdd(&a.ctr->spills, 1ull);
                 if (idx < a.spill_cap) {
-                    a.spill[idx].n = n0 + 128ull * j + 2ull * bit;
+                    a.spill[idx].n = n0 + 2ull * r + 384ull * m + 6ull * bit;
                     a.spill[idx].iv = ivx;
                     a.spill[idx].p = 0;
                 }
