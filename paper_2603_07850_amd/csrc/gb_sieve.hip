@@ -342,11 +342,15 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                 // i = (xr - 2t) / 6 (mod p)
                 uint32_t ph[9];
                 uint32_t dec[9];
+                // (32 * tid) mod p is recomputed here rather than kept live
+                // across the segment loop, where it would be spilled
+                uint32_t tt = tid;
+                asm volatile("" : "+v"(tt));
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
                     const uint32_t p = kPre[i + 1];
                     const uint32_t phi = (((xr[i] + 2 * p - 2 * t) % p) * kInv6[i]) % p;
-                    ph[i] = (phi + p - (32u * tid) % p) % p;   // (phi - 32w) mod p at w = tid
+                    ph[i] = (phi + p - (32u * tt) % p) % p;   // (phi - 32w) mod p at w = tid
                     dec[i] = (32u * NT) % p;
                 }
                 const uint32_t *__restrict__ bmt = bm ? bm + t * WCU : nullptr;
