@@ -85,8 +85,8 @@ struct GbProbeArgs {
 
 // The segment window in LDS is stored by class: odd bit b (odd number
 // q_lo + 2b) is bit b / 3 of class array b mod 3.  One class holds the
-// multiples of 3 (the class t3 with q_lo + 2*t3 = 0 mod 3); the other two hold
-// everything else.  The halo H is a multiple of 96, so class index
+// multiples of 3 (the class t3 with q_lo + 2*t3 = 0 mod 3) and is not stored;
+// classes t3 + 1 and t3 + 2 (mod 3) are kept in LDS slots 0 and 1.  The halo H is a multiple of 96, so class index
 // b / 3 = i' + H/3 + (r - h - t)/3 for b = r + 3i' + H - h.
 constexpr uint32_t kHaloMax = 32832;  // largest halo: multiple of 96 >= 32767 + 2
 
@@ -101,7 +101,8 @@ constexpr uint32_t gb_class_words(int log2e)
 // the evens, class t3 of the multiples of 3): the odd primes p <= 65536 whose
 // n - p avoids class t3 (the others cannot be prime, n - p = 3 aside), in
 // ascending order.  Entry: {byte offset, to subtract from the lane's base,
-// of the first LDS word holding bit(n - p); funnel-shift amount; p minus the
+// of the first LDS word holding bit(n - p), slot of its class included;
+// funnel-shift amount; p minus the
 // previous entry's p (0 before the first)}.  Table (lg, r, t3) starts at entry
 // ((lg - 18) * 9 + r * 3 + t3) * kCandStride.
 constexpr uint32_t kCandStride = 6560;

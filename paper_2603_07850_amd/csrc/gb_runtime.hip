@@ -345,7 +345,8 @@ gb_status build_table(Ctx &c, uint64_t limit)
                     const int64_t d = (r - h - t) / 3;                   // exact
                     const int64_t fw = d >= 0 ? d / 32 : -((-d + 31) / 32);  // floor(d / 32)
                     uint32_t *te = &tab[(base + e_) * 3];
-                    te[0] = (uint32_t)(-4 * (t * WC + fw));
+                    const int64_t slot = (t + 2 - t3) % 3;          // stored class arrays
+                    te[0] = (uint32_t)(-4 * (slot * WC + fw));
                     te[1] = (uint32_t)(d - 32 * fw);
                     te[2] = pk - prev;
                     ptab[base + e_] = pk;

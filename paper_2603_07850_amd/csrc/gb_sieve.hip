@@ -180,7 +180,7 @@ __device__ __forceinline__ uint32_t count_le(const uint32_t *primes, uint64_t np
 }
 
 // Clear the odd bits j, j + p, ... below weff (one prime, one thread) in the
-// class arrays of the window; bits of class t3 (multiples of 3) stay zero.  A
+// class arrays of the window; class t3 (multiples of 3) is not stored.  A
 // prime below the window strikes many bits: its multiples in each of the two
 // other classes t are the class indices i_t, i_t + p, ..., so each class gets
 // a plain strided loop.  A larger prime strikes at most once.
@@ -196,7 +196,7 @@ __device__ __forceinline__ void strike_prime(uint32_t *bits, uint32_t weff, uint
             const uint32_t t = (t3 + s2) % 3;
             const uint32_t kt = ((t + 3 - jm) * pm) % 3;  // j + kt*p = t (mod 3)
             const uint32_t bt = j + kt * p;
-            uint32_t *cw = bits + t * WC;
+            uint32_t *cw = bits + (s2 - 1) * WC;             // class t is kept in slot s2 - 1
             const uint32_t lim = (weff + 2 - t) / 3;       // class indices in the window
             for (uint32_t i = (bt - t) / 3; i < lim; i += p)
                 atomicAnd(&cw[i >> 5], ~(1u << (i & 31)));
@@ -205,7 +205,7 @@ __device__ __forceinline__ void strike_prime(uint32_t *bits, uint32_t weff, uint
         const uint32_t i = __umulhi(j, 0xAAAAAAABu) >> 1;  // j / 3
         const uint32_t t = j - 3 * i;
         if (t != t3)
-            atomicAnd(&bits[__umul24(t, WC) + (i >> 5)], ~(1u << (i & 31)));
+            atomicAnd(&bits[__umul24((t + 2 - t3) % 3, WC) + (i >> 5)], ~(1u << (i & 31)));
     }
 }
 
@@ -243,7 +243,7 @@ __device__ __forceinline__ bool small_prime_35(int64_t q)
 // at most eight waves each): the register budget is set to match it.
 constexpr uint32_t lds_waves_per_simd(int log2e, int nt)
 {
-    const uint32_t wg_bytes = (uint32_t)(((1u << log2e) + kHaloMax) / 8) + 1024;
+    const uint32_t wg_bytes = 2 * 4 * gb_class_words(log2e) + 1024;
     const uint32_t wgs = (160u * 1024u) / wg_bytes;
     const uint32_t w = wgs * (uint32_t)(nt / 64) / 4;
     return w < 1 ? 1 : (w > 8 ? 8 : w);
@@ -258,7 +258,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
     constexpr uint32_t NWAVE = NT / 64;
     // primes up to this bound strike a window >= 1024 times: one wave each
     constexpr uint32_t kWaveTierMax = (uint32_t)(E >> 9);
-    __shared__ uint32_t bits[3 * WC];
+    __shared__ uint32_t bits[2 * WC];   // classes t3 + 1 and t3 + 2 (mod 3)
     __shared__ unsigned long long sh_seg;
     __shared__ uint32_t sh_nroot;
     __shared__ unsigned long long red_sum[NWAVE];
@@ -321,7 +321,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                 sh_nroot = c;
         }
 
-        // ---- presieve: class t3 is all multiples of 3; periodic masks of 5..31 ----
+        // ---- presieve: periodic masks of 5..31 in the two stored classes ----
         {
             const uint32_t *__restrict__ bm =
                 a.bitmap ? a.bitmap + (seg - a.seg_base) * (uint64_t)(3 * WCU) : nullptr;
@@ -331,13 +331,9 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                 const uint32_t p = kPre[i + 1];
                 xr[i] = neg ? (uint32_t)(qneg % p) : (uint32_t)((p - qlo % p) % p);
             }
-            for (uint32_t t = 0; t < 3; ++t) {
-                uint32_t *cw = bits + t * WC;
-                if (t == t3) {
-                    for (uint32_t w = tid; w < WCU; w += NT)
-                        cw[w] = 0u;
-                    continue;
-                }
+            for (uint32_t sl = 0; sl < 2; ++sl) {
+                const uint32_t t = (t3 + 1 + sl) % 3;
+                uint32_t *cw = bits + sl * WC;
                 // class index i is q = q_lo + 2t + 6i: a multiple of p when
                 // i = (xr - 2t) / 6 (mod p)
                 uint32_t ph[9];
@@ -370,9 +366,10 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
             __syncthreads();
             const uint64_t bmax = neg ? (35 + qneg) >> 1 : (35 - qlo) >> 1;  // odd bits 0..bmax
             const uint32_t wmax = (uint32_t)((bmax / 3) >> 5);
-            for (uint32_t t = 0; t < 3; ++t) {
+            for (uint32_t sl = 0; sl < 2; ++sl) {
+                const uint32_t t = (t3 + 1 + sl) % 3;
                 for (uint32_t w = tid; w <= wmax; w += NT) {
-                    uint32_t v = bits[t * WC + w];
+                    uint32_t v = bits[sl * WC + w];
                     for (uint32_t k = 0; k < 32; ++k) {
                         const uint64_t b = 3ull * (32 * w + k) + t;
                         if (b > bmax)
@@ -380,7 +377,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                         const int64_t q = neg ? (int64_t)(2 * b) - (int64_t)qneg : (int64_t)(qlo + 2 * b);
                         v = small_prime_35(q) ? (v | (1u << k)) : (v & ~(1u << k));
                     }
-                    bits[t * WC + w] = v;
+                    bits[sl * WC + w] = v;
                 }
             }
         }
@@ -409,7 +406,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                     if (bt < weff && it < lim) {
                         const uint32_t mask = ~(1u << (it & 31));
                         const uint32_t wend = (lim + 31) >> 5;
-                        uint32_t *cw = bits + t * WC;
+                        uint32_t *cw = bits + (s2 - 1) * WC;
                         for (uint32_t w = (uint32_t)(it >> 5); w < wend; w += 2 * p)
                             atomicAnd(&cw[w], mask);
                     }
