@@ -239,11 +239,101 @@ __device__ __forceinline__ bool small_prime_35(int64_t q)
            q == 29 || q == 31;
 }
 
+// Settle a lane's block after its grouped entries (called by whole waves):
+// the entries after the last full group one at a time, the gap-form checksum
+// correction for evens still open, the replay of the last group with a hit
+// (its last hitting entry is the block's largest p_min, the lowest bit of that
+// hit the smallest n attaining it; every entry replayed was tested before, so
+// the replay reproduces the same hits), and the spill of evens still open.
+// Bit i of the block is the even nbase + 6i.
+__device__ __forceinline__ void finish_block(const GbProbeArgs &a, const char *lds, uint32_t base4,
+                                             uint32_t tab, uint32_t nv, uint32_t k, uint32_t ul,
+                                             uint32_t uh, uint32_t acc, uint32_t lastg,
+                                             uint32_t gl, uint32_t gh, uint32_t open0,
+                                             uint64_t nbase, uint32_t ivx, uint64_t &sum,
+                                             uint32_t &nres, uint32_t &bestp, uint64_t &bestn)
+{
+    const ccand_t ct = (ccand_t)(a.ctab + (uint64_t)tab * 3 * kCandStride);
+    const cprime_t pt = (cprime_t)(a.ptab + (uint64_t)tab * kCandStride);
+    if (__ballot((ul | uh) != 0) != 0) {
+        for (; k <= nv; ++k) {
+            const uint32_t sl = ul, sh = uh;
+            probe_one(lds, base4, ct[k - 1].off, ct[k - 1].sh, ct[k - 1].gap, ul, uh, acc);
+            const bool any = (ul != sl) | (uh != sh);
+            lastg = any ? k : lastg;
+            gl = any ? sl : gl;
+            gh = any ? sh : gh;
+            if (__ballot((ul | uh) != 0) == 0) {
+                ++k;
+                break;
+            }
+        }
+    }
+    // entry k - 1 is the last one the wave tested
+    const uint32_t open = (uint32_t)(__popc(ul) + __popc(uh));
+    if (open && k > 1)
+        acc -= pt[k - 2] * open;
+    // a second-pass block's share is negative when it only spills evens (the
+    // first pass already counted their entries), so acc is a signed value of
+    // magnitude < 2^31 and is added sign-extended
+    sum += (uint64_t)(int64_t)(int32_t)acc;
+    nres += open0 - open;
+    if (lastg) {
+        uint32_t vl = gl, vh = gh, lastp = 0, hl = 0, hh = 0;
+        const uint32_t kend = lastg + 3 < nv ? lastg + 3 : nv;
+        const uint32_t *tabv = a.ctab + (uint64_t)tab * 3 * kCandStride;
+        const uint32_t *ptv = a.ptab + (uint64_t)tab * kCandStride;
+        for (uint32_t kk = lastg; kk <= kend && (vl | vh); ++kk) {
+            const uint32_t *e = tabv + 3 * (kk - 1);
+            const uint32_t addr = base4 - e[0];
+            const uint32_t w0 = *(const uint32_t *)(lds + addr);
+            const uint32_t w1 = *(const uint32_t *)(lds + addr + 4);
+            const uint32_t w2 = *(const uint32_t *)(lds + addr + 8);
+            const uint32_t xl = __builtin_amdgcn_alignbit(w1, w0, e[1]) & vl;
+            const uint32_t xh = __builtin_amdgcn_alignbit(w2, w1, e[1]) & vh;
+            if (xl | xh) {
+                vl ^= xl;
+                vh ^= xh;
+                lastp = ptv[kk - 1];
+                hl = xl;
+                hh = xh;
+            }
+        }
+        if (lastp > bestp) {
+            bestp = lastp;
+            const uint32_t bit = hl ? (uint32_t)(__ffs(hl) - 1) : 32u + (uint32_t)(__ffs(hh) - 1);
+            bestn = nbase + 6ull * bit;
+        }
+    }
+    while (ul | uh) {
+        uint32_t bit;
+        if (ul) {
+            bit = __ffs(ul) - 1;
+            ul &= ul - 1;
+        } else {
+            bit = 32 + __ffs(uh) - 1;
+            uh &= uh - 1;
+        }
+        const unsigned long long idx = atomicAdd(&a.ctr->spills, 1ull);
+        if (idx < a.spill_cap) {
+            a.spill[idx].n = nbase + 6ull * bit;
+            a.spill[idx].iv = ivx;
+            a.spill[idx].p = 0;
+        }
+    }
+}
+
+// Second-pass queue entries per class of evens (a fifth of a class's blocks).
+constexpr uint32_t gb_probe_queue(int log2e)
+{
+    return 1u << (log2e - 10);
+}
+
 // Waves per SIMD that the LDS window allows (160 KB of LDS per CU, four SIMDs,
 // at most eight waves each): the register budget is set to match it.
 constexpr uint32_t lds_waves_per_simd(int log2e, int nt)
 {
-    const uint32_t wg_bytes = 2 * 4 * gb_class_words(log2e) + 1024;
+    const uint32_t wg_bytes = 2 * 4 * gb_class_words(log2e) + 30 * gb_probe_queue(log2e) + 1024;
     const uint32_t wgs = (160u * 1024u) / wg_bytes;
     const uint32_t w = wgs * (uint32_t)(nt / 64) / 4;
     return w < 1 ? 1 : (w > 8 ? 8 : w);
@@ -259,6 +349,12 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
     // primes up to this bound strike a window >= 1024 times: one wave each
     constexpr uint32_t kWaveTierMax = (uint32_t)(E >> 9);
     __shared__ uint32_t bits[2 * WC];   // classes t3 + 1 and t3 + 2 (mod 3)
+    // second-pass queues, one per class of evens: block index and open masks
+    constexpr uint32_t kQueue = gb_probe_queue(LOG2E);
+    __shared__ uint16_t qm[3][kQueue];
+    __shared__ uint32_t ql[3][kQueue];
+    __shared__ uint32_t qh[3][kQueue];
+    __shared__ uint32_t qn[3];
     __shared__ unsigned long long sh_seg;
     __shared__ uint32_t sh_nroot;
     __shared__ unsigned long long red_sum[NWAVE];
@@ -321,6 +417,8 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                 sh_nroot = c;
         }
 
+        if (tid < 3)
+            qn[tid] = 0;   // published by the barrier after the presieve
         // ---- presieve: periodic masks of 5..31 in the two stored classes ----
         {
             const uint32_t *__restrict__ bm =
@@ -456,6 +554,14 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
         // of a block is accumulated in gap form: the sum of p_min over the evens
         // resolved by entries 1..K equals the sum over k of gap_k * (evens open
         // before k), minus p_K per even still open after K.
+        //
+        // Two passes: a wave runs in lockstep until its slowest block is done,
+        // and a 64-even block needs far fewer entries on average than the worst
+        // of 64 blocks.  The first pass gives every block ka groups of entries
+        // (about 0.28 groups per bit of n, enough for all but a few blocks);
+        // blocks still open then go to a per-class queue in LDS, and the second
+        // pass packs 64 of them per wave and continues from entry 4*ka + 1.  A
+        // block that finds its queue full simply continues in the first pass.
         const char *lds = (const char *)bits;
         uint64_t sum = 0;
         uint32_t nres = 0;
@@ -478,6 +584,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                 bestn = 6;
             }
         }
+        const uint32_t ka = ((64u - (uint32_t)__builtin_clzll(n0)) * 277u + 999u) / 1000u;
         uint32_t cntc[3], nblkc[3], nwbc[3];
 #pragma unroll
         for (uint32_t r = 0; r < 3; ++r) {
@@ -510,8 +617,6 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
             const uint32_t open0 = (uint32_t)(__popc(ul) + __popc(uh));
             const uint32_t tab = tabbase + r * 3 + t3;
             const cgroup_t gt = (cgroup_t)(a.ctab + (uint64_t)tab * 3 * kCandStride);
-            const ccand_t ct = (ccand_t)(a.ctab + (uint64_t)tab * 3 * kCandStride);
-            const cprime_t pt = (cprime_t)(a.ptab + (uint64_t)tab * kCandStride);
             const uint32_t nv = a.nv[r * 3 + t3];
             const uint32_t ngrp = nv >> 2;
             const uint32_t base4 = ((act ? 2 * m : 0) + H96) * 4;  // byte address of the lane's first word
@@ -519,80 +624,67 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
             uint32_t lastg = 0;   // first entry of the last group with a hit
             uint32_t gl = 0;      // open evens at the start of that group
             uint32_t gh = 0;
+            uint32_t qopen = 0;   // evens handed to the second pass
             uint32_t k = 1;       // next entry (1-based)
             for (uint32_t g = 0; g < ngrp; ++g) {
+                if (g == ka) {
+                    if (ul | uh) {
+                        const uint32_t slot = atomicAdd(&qn[r], 1u);
+                        if (slot < kQueue) {
+                            qm[r][slot] = (uint16_t)m;
+                            ql[r][slot] = ul;
+                            qh[r][slot] = uh;
+                            qopen = (uint32_t)(__popc(ul) + __popc(uh));
+                            ul = 0;
+                            uh = 0;
+                        }
+                    }
+                    if (__ballot((ul | uh) != 0) == 0)
+                        break;
+                }
                 probe_group(lds, base4, gt + g, k, ul, uh, acc, lastg, gl, gh);
                 k += 4;
                 if (__ballot((ul | uh) != 0) == 0)
                     break;
             }
-            // the entries after the last full group, one at a time
-            if (__ballot((ul | uh) != 0) != 0) {
-                for (; k <= nv; ++k) {
-                    const uint32_t sl = ul, sh = uh;
-                    probe_one(lds, base4, ct[k - 1].off, ct[k - 1].sh, ct[k - 1].gap, ul, uh, acc);
-                    const bool any = (ul != sl) | (uh != sh);
-                    lastg = any ? k : lastg;
-                    gl = any ? sl : gl;
-                    gh = any ? sh : gh;
-                    if (__ballot((ul | uh) != 0) == 0) {
-                        ++k;
+            finish_block(a, lds, base4, tab, nv, k, ul, uh, acc, lastg, gl, gh, open0 - qopen,
+                         n0 + 2ull * r + 384ull * m, ivx, sum, nres, bestp, bestn);
+        }
+        __syncthreads();
+        // second pass over the queued blocks, 64 per wave, class by class
+        {
+            uint32_t nqc[3], nqwb[3];
+#pragma unroll
+            for (uint32_t r = 0; r < 3; ++r) {
+                const uint32_t q = qn[r];
+                nqc[r] = q < kQueue ? q : kQueue;
+                nqwb[r] = (nqc[r] + 63) >> 6;
+            }
+            const uint32_t nwb2 = nqwb[0] + nqwb[1] + nqwb[2];
+            for (uint32_t wb = wv; wb < nwb2; wb += NWAVE) {
+                const uint32_t r = wb < nqwb[0] ? 0u : (wb < nqwb[0] + nqwb[1] ? 1u : 2u);
+                const uint32_t wb0 = r == 0 ? 0u : (r == 1 ? nqwb[0] : nqwb[0] + nqwb[1]);
+                const uint32_t e = (wb - wb0) * 64 + lane;
+                const bool act = e < nqc[r];
+                const uint32_t m = act ? (uint32_t)qm[r][e] : 0u;
+                uint32_t ul = act ? ql[r][e] : 0u;
+                uint32_t uh = act ? qh[r][e] : 0u;
+                const uint32_t open0 = (uint32_t)(__popc(ul) + __popc(uh));
+                const uint32_t tab = tabbase + r * 3 + t3;
+                const cgroup_t gt = (cgroup_t)(a.ctab + (uint64_t)tab * 3 * kCandStride);
+                const uint32_t nv = a.nv[r * 3 + t3];
+                const uint32_t ngrp = nv >> 2;
+                const uint32_t base4 = (2 * m + H96) * 4;
+                uint32_t acc = 0, lastg = 0, gl = 0, gh = 0;
+                uint32_t k = 4 * ka + 1;
+                for (uint32_t g = ka; g < ngrp; ++g) {
+                    probe_group(lds, base4, gt + g, k, ul, uh, acc, lastg, gl, gh);
+                    k += 4;
+                    if (__ballot((ul | uh) != 0) == 0)
                         break;
-                    }
                 }
-            }
-            // entry k - 1 is the last one the wave tested
-            const uint32_t open = (uint32_t)(__popc(ul) + __popc(uh));
-            if (open && k > 1)
-                acc -= pt[k - 2] * open;
-            sum += acc;
-            nres += open0 - open;
-            // Replay the last group with a hit: its last hitting entry is the
-            // block's largest p_min, and the lowest bit of that hit is the
-            // smallest n attaining it.  Every entry replayed here was also
-            // tested above, so the replay reproduces the same hits.
-            if (lastg) {
-                uint32_t vl = gl, vh = gh, lastp = 0, hl = 0, hh = 0;
-                const uint32_t kend = lastg + 3 < nv ? lastg + 3 : nv;
-                const uint32_t *tabv = a.ctab + (uint64_t)tab * 3 * kCandStride;
-                const uint32_t *ptv = a.ptab + (uint64_t)tab * kCandStride;
-                for (uint32_t kk = lastg; kk <= kend && (vl | vh); ++kk) {
-                    const uint32_t *e = tabv + 3 * (kk - 1);
-                    const uint32_t addr = base4 - e[0];
-                    const uint32_t w0 = *(const uint32_t *)(lds + addr);
-                    const uint32_t w1 = *(const uint32_t *)(lds + addr + 4);
-                    const uint32_t w2 = *(const uint32_t *)(lds + addr + 8);
-                    const uint32_t xl = __builtin_amdgcn_alignbit(w1, w0, e[1]) & vl;
-                    const uint32_t xh = __builtin_amdgcn_alignbit(w2, w1, e[1]) & vh;
-                    if (xl | xh) {
-                        vl ^= xl;
-                        vh ^= xh;
-                        lastp = ptv[kk - 1];
-                        hl = xl;
-                        hh = xh;
-                    }
-                }
-                if (lastp > bestp) {
-                    bestp = lastp;
-                    const uint32_t bit = hl ? (uint32_t)(__ffs(hl) - 1) : 32u + (uint32_t)(__ffs(hh) - 1);
-                    bestn = n0 + 2ull * r + 384ull * m + 6ull * bit;
-                }
-            }
-            while (ul | uh) {
-                uint32_t bit;
-                if (ul) {
-                    bit = __ffs(ul) - 1;
-                    ul &= ul - 1;
-                } else {
-                    bit = 32 + __ffs(uh) - 1;
-                    uh &= uh - 1;
-                }
-                const unsigned long long idx = atomicAdd(&a.ctr->spills, 1ull);
-                if (idx < a.spill_cap) {
-                    a.spill[idx].n = n0 + 2ull * r + 384ull * m + 6ull * bit;
-                    a.spill[idx].iv = ivx;
-                    a.spill[idx].p = 0;
-                }
+                finish_block(a, lds, base4, tab, nv, k, ul, uh, acc, lastg, gl, gh, open0,
+                             n0 + 2ull * r + 384ull * m, ivx, sum, nres, bestp, bestn);
             }
         }
 
