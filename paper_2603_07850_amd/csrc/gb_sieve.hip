@@ -558,7 +558,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
         // Two passes: a wave runs in lockstep until its slowest block is done,
         // and a 64-even block needs far fewer entries on average than the worst
         // of 64 blocks.  The first pass gives every block ka groups of entries
-        // (about 0.28 groups per bit of n, enough for all but a few blocks);
+        // (0.31 groups per bit of n, the best of a sweep at [4, 10^12]);
         // blocks still open then go to a per-class queue in LDS, and the second
         // pass packs 64 of them per wave and continues from entry 4*ka + 1.  A
         // block that finds its queue full simply continues in the first pass.
@@ -584,7 +584,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                 bestn = 6;
             }
         }
-        const uint32_t ka = ((64u - (uint32_t)__builtin_clzll(n0)) * 277u + 999u) / 1000u;
+        const uint32_t ka = ((64u - (uint32_t)__builtin_clzll(n0)) * 310u + 999u) / 1000u;
         uint32_t cntc[3], nblkc[3], nwbc[3];
 #pragma unroll
         for (uint32_t r = 0; r < 3; ++r) {
