@@ -120,7 +120,7 @@ def cpu_baseline(sample_windows):
                       % (len(wins), ev, cores, dt)}
 
 
-def run_batched(gb, steps, per_interval=True):
+def run_batched(gb, steps, per_interval=True, tune=False):
     """4096 seeded uneven intervals: one persistent launch vs one launch each."""
     import statistics
 
@@ -128,6 +128,9 @@ def run_batched(gb, steps, per_interval=True):
     ivs = Wl.batch_intervals()
     ev = sum(evens_in(a, b) for a, b in ivs)
     gb.base_primes(2**32 - 1)
+    if tune:
+        log("batched: tuning on every 8th interval")
+        gb.autotune_batch(ivs[::8], 65536)
     gb.verify_batch(ivs[:64], 65536)
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -138,7 +141,7 @@ def run_batched(gb, steps, per_interval=True):
     if not per_interval:
         return {"intervals": len(ivs), "evens": ev, "batched_evens_per_s": ev / dt,
                 "batched_s": dt, "p50_ms": q(lat, 0.5) * 1e3, "p99_ms": q(lat, 0.99) * 1e3,
-                "all_verified": all(r["n_failed"] == 0 for r in res)}
+                "all_verified": all(r["n_failed"] == 0 for r in res), "params": gb.get_params()}
     log("batched: %d intervals in %.3f s per launch; per-interval baseline next" % (len(ivs), dt))
     t0 = time.perf_counter()
     done = []
@@ -156,6 +159,7 @@ def run_batched(gb, steps, per_interval=True):
         "per_interval_p50_ms": q(done, 0.5) * 1e3, "per_interval_p99_ms": q(done, 0.99) * 1e3,
         "all_verified": all(r["n_failed"] == 0 for r in res),
         "median_batched_latency_ms": statistics.median(lat) * 1e3,
+        "params": gb.get_params(),
     }
 
 
@@ -310,11 +314,13 @@ def main():
         "roofline": roofline,
     }
     if args.batched or args.served:
-        # batches reach 2^64: automatic strike-bitmap policy for the other legs
-        p = gb.get_params()
-        p["bucket_log2"] = 0
-        gb.set_params(**p)
-        out["batched"] = run_batched(gb, 2)
+        # batches reach 2^64: their launch parameters come from the batch
+        # autotuner on every 8th interval of the batch (unless --params)
+        if args.params:
+            p = gb.get_params()
+            p["bucket_log2"] = 0
+            gb.set_params(**p)
+        out["batched"] = run_batched(gb, 2, tune=not args.params)
     if args.served:
         out["served"] = run_served(gb, out["batched"]["batched_evens_per_s"])
     if not args.no_cpu_baseline:

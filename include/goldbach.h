@@ -174,6 +174,18 @@ gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream,
                       gb_params *best);
 
 /*
+ * Autotuner for the batched form (the calibration-batch tuner): time
+ * gb_verify_batch over the k intervals AB[0..2k) (the caller passes a sample
+ * of the batches it will run; at most 2^36 evens in all) under each segment
+ * size, workgroup size, probe window and strike-bitmap bound (automatic,
+ * 2^(seg_log2+3), 2^(seg_log2+5)), keep the fastest as the current
+ * parameters and write it to *best (may be NULL).  Results of later calls do
+ * not depend on the choice.  GB_EINVAL for an empty or oversized sample.
+ */
+gb_status gb_autotune_batch(const uint64_t *AB, uint64_t k, uint64_t P_max, void *stream,
+                            gb_params *best);
+
+/*
  * Deterministic Miller-Rabin primality of `count` u64 values (Sec. 3.4: the
  * first twelve primes as bases; 128-bit products).  q and is_prime are DEVICE
  * pointers (count * 8 and count bytes); is_prime[i] becomes 1 or 0.  This is

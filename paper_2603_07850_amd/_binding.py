@@ -88,6 +88,7 @@ def lib():
         "gb_set_params": (st, [ctypes.POINTER(Params)]),
         "gb_get_params": (st, [ctypes.POINTER(Params)]),
         "gb_autotune": (st, [u64, u64, u64, vp, ctypes.POINTER(Params)]),
+        "gb_autotune_batch": (st, [ctypes.POINTER(ctypes.c_uint64), u64, u64, vp, ctypes.POINTER(Params)]),
         "gb_is_prime_u64": (st, [vp, u64, vp, vp]),
         "gb_last_stats": (st, [ctypes.POINTER(Stats)]),
         "gb_last_latencies": (st, [vp, u64]),
@@ -205,6 +206,18 @@ def get_params():
 def autotune(A, B, P_max, stream=None):
     p = Params()
     _check(lib().gb_autotune(int(A), int(B), int(P_max), _stream(stream), ctypes.byref(p)))
+    return p.as_dict()
+
+
+def autotune_batch(intervals, P_max, stream=None):
+    """Choose the launch parameters by timing gb_verify_batch on a sample batch."""
+    k = len(intervals)
+    AB = (ctypes.c_uint64 * (2 * max(k, 1)))()
+    for i, (a, b) in enumerate(intervals):
+        AB[2 * i] = int(a)
+        AB[2 * i + 1] = int(b)
+    p = Params()
+    _check(lib().gb_autotune_batch(AB, k, int(P_max), _stream(stream), ctypes.byref(p)))
     return p.as_dict()
 
 

@@ -1002,46 +1002,36 @@ gb_status gb_get_params(gb_params *p)
     return GB_OK;
 }
 
-gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream, gb_params *best)
+namespace {
+
+// Time verify_many over the given intervals under each launch shape (and
+// strike-bitmap bound when `bounds` holds more than one) and keep the fastest.
+gb_status tune(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, hipStream_t s,
+               const std::vector<uint32_t> &bounds, bool rel_bounds, gb_params *best)
 {
-    Ctx &c = ctx();
-    std::lock_guard<std::mutex> lk(c.mu);
-    g_err.clear();
-    GB_TRY(use_device(c));
-    uint64_t An, Bn;
-    if (!normalize(A, B, &An, &Bn) || (Bn - An) / 2 + 1 > (1ull << 36)) {
-        set_err("calibration range must be non-empty and hold at most 2^36 evens");
-        return GB_EINVAL;
-    }
     const gb_params saved = c.params;
     const uint32_t logs[3] = {18, 19, 20};
     const uint32_t wgs[3] = {256, 512, 1024};
     const uint32_t wins[2] = {4096, 16384};
-    // the bucket bound matters only when the range reaches primes above the
-    // smallest automatic bound, 2^22
-    const bool big = isqrt_u64(Bn) > (1ull << 22);
-    const uint32_t blogs[2] = {0, 32};
-    const int nb = big ? 2 : 1;
     double best_t = 1e300;
     gb_params best_p = saved;
-    const uint64_t AB[2] = {A, B};
-    hipStream_t s = (hipStream_t)stream;
+    std::vector<gb_result> out(k);
     for (uint32_t lg : logs)
         for (uint32_t wg : wgs)
             for (uint32_t win : wins)
-                for (int bi = 0; bi < nb; ++bi) {
-                    gb_params p = {lg, wg, win, 0, big ? blogs[bi] : saved.bucket_log2, saved.bucket_mib};
+                for (uint32_t bd : bounds) {
+                    const uint32_t blog = rel_bounds && bd ? lg + bd : bd;
+                    gb_params p = {lg, wg, win, 0, blog, saved.bucket_mib};
                     int occ = 0;
                     if (gb_probe_occupancy((int)lg, (int)wg, &occ) != hipSuccess || occ < 1) {
                         (void)hipGetLastError();
                         continue;
                     }
                     c.params = p;
-                    gb_result r = {};
                     double tmin = 1e300;
                     for (int rep = 0; rep < 2; ++rep) {
                         const auto t0 = std::chrono::steady_clock::now();
-                        gb_status st = verify_many(c, AB, 1, P_max, s, &r, false);
+                        gb_status st = verify_many(c, AB, k, P_max, s, out.data(), false);
                         const auto t1 = std::chrono::steady_clock::now();
                         if (st != GB_OK && st != GB_ETRUNC) {
                             c.params = saved;
@@ -1058,6 +1048,54 @@ gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream, gb_p
     if (best)
         *best = best_p;
     return GB_OK;
+}
+
+}  // namespace
+
+gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream, gb_params *best)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    g_err.clear();
+    GB_TRY(use_device(c));
+    uint64_t An, Bn;
+    if (!normalize(A, B, &An, &Bn) || (Bn - An) / 2 + 1 > (1ull << 36)) {
+        set_err("calibration range must be non-empty and hold at most 2^36 evens");
+        return GB_EINVAL;
+    }
+    // the bucket bound matters only when the range reaches primes above the
+    // smallest automatic bound, 2^22
+    std::vector<uint32_t> bounds = {c.params.bucket_log2};
+    if (isqrt_u64(Bn) > (1ull << 22))
+        bounds = {0, 32};
+    const uint64_t AB[2] = {A, B};
+    return tune(c, AB, 1, P_max, (hipStream_t)stream, bounds, false, best);
+}
+
+gb_status gb_autotune_batch(const uint64_t *AB, uint64_t k, uint64_t P_max, void *stream,
+                            gb_params *best)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    g_err.clear();
+    GB_TRY(use_device(c));
+    if (k == 0 || !AB) {
+        set_err("calibration batch must hold at least one interval");
+        return GB_EINVAL;
+    }
+    uint64_t evens = 0;
+    for (uint64_t i = 0; i < k; ++i) {
+        uint64_t An, Bn;
+        if (normalize(AB[2 * i], AB[2 * i + 1], &An, &Bn))
+            evens += (Bn - An) / 2 + 1;
+    }
+    if (evens == 0 || evens > (1ull << 36)) {
+        set_err("calibration batch must hold between 1 and 2^36 evens");
+        return GB_EINVAL;
+    }
+    // automatic bound, and bounds 2^(seg_log2 + 3) and 2^(seg_log2 + 5)
+    const std::vector<uint32_t> bounds = {0, 3, 5};
+    return tune(c, AB, k, P_max, (hipStream_t)stream, bounds, true, best);
 }
 
 gb_status gb_is_prime_u64(const uint64_t *q, uint64_t count, uint8_t *is_prime, void *stream)

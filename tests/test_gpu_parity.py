@@ -280,3 +280,26 @@ def test_bucket_batch_equals_single(gb, O):
                 assert g[f] == s[f] == o[f], (f, A, B)
     finally:
         gb.set_params(**saved)
+
+
+def test_batch_autotuner_keeps_results(gb, O):
+    """The batch autotuner only changes launch parameters: the batch verified
+    under the parameters it picks equals the oracle."""
+    table(gb, 2**32 - 1)
+    saved = gb.get_params()
+    try:
+        ivs = [(10**9, 10**9 + 200000), (U64 - 300000, U64), (10**15, 10**15 + 2 * 77777),
+               (4, 60000), (2**50 + 2, 2**50 + 2 + 2 * 150000)]
+        p = gb.autotune_batch(ivs, 65536)
+        assert p["seg_log2"] in (18, 19, 20) and p["wg_size"] in (256, 512, 1024)
+        assert gb.get_params() == p
+        got = gb.verify_batch(ivs, 65536)
+        for (A, B), g in zip(ivs, got):
+            o = O.verify_range(A, B, 65536, 2**32 - 1, seg_evens=1 << 22)
+            for f in FIELDS:
+                assert g[f] == o[f], (f, A, B)
+        with pytest.raises(gb.GoldbachError) as e:
+            gb.autotune_batch([], 65536)
+        assert e.value.name == "GB_EINVAL"
+    finally:
+        gb.set_params(**saved)
