@@ -303,3 +303,30 @@ def test_batch_autotuner_keeps_results(gb, O):
         assert e.value.name == "GB_EINVAL"
     finally:
         gb.set_params(**saved)
+
+
+@pytest.mark.parametrize("shape", [(18, 512), (19, 1024), (20, 256)])
+@pytest.mark.parametrize("P_max", [600, 1000, 4096])
+def test_two_pass_probe_and_queue_overflow(gb, O, shape, P_max):
+    """Blocks handed to the probe's second pass, and (with small P_max, where many
+    blocks stay open after the first pass) blocks that find the queue full and
+    finish in the first pass, with spills to Phase 2: identical to the oracle."""
+    saved = gb.get_params()
+    try:
+        gb.set_params(seg_log2=shape[0], wg_size=shape[1], window=4096)
+        check(gb, O, 10**12, 10**12 + 2 * 3_000_000, P_max, 1_100_000, cap=1 << 20)
+    finally:
+        gb.set_params(**saved)
+
+
+def test_range_autotuner_keeps_results(gb, O):
+    """The range autotuner only changes launch parameters."""
+    table(gb, 10**6)
+    saved = gb.get_params()
+    try:
+        p = gb.autotune(10**11, 10**11 + 2 * 4_000_000, 65536)
+        assert p["seg_log2"] in (18, 19, 20) and p["wg_size"] in (256, 512, 1024)
+        assert gb.get_params() == p
+        check(gb, O, 10**11, 10**11 + 2 * 4_000_000, 65536, 10**6)
+    finally:
+        gb.set_params(**saved)
