@@ -33,57 +33,72 @@ __device__ __forceinline__ void strike(const GbBucketArgs &a, uint64_t g, uint32
     atomicOr(&a.bitmap[rel * a.words + t * a.wcu + (i >> 5)], 1u << (i & 31));
 }
 
+// Tasks and chunks are read-only here: read through the constant address
+// space, with uniform indices, they load as scalars.
+typedef const __attribute__((address_space(4))) GbFillTask *ctask_t;
+typedef const __attribute__((address_space(4))) GbChunk *cchunk_t;
+
 __device__ void fill_tile(const GbBucketArgs &a, uint64_t tile)
 {
+    const ctask_t task = (ctask_t)a.task;
+    const cchunk_t chunk = (cchunk_t)a.chunk;
     uint32_t lo = 0, hi = a.ntask - 1;   // last task whose first tile <= tile
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) >> 1;
-        if (a.task[mid].tile_first <= tile)
+        if (task[mid].tile_first <= tile)
             lo = mid;
         else
             hi = mid - 1;
     }
-    const GbFillTask T = a.task[lo];
+    const uint64_t t_first = task[lo].tile_first;
+    const uint32_t c_first = task[lo].chunk_first;
+    const uint32_t c_n = task[lo].nchunk;
+    const uint32_t p_first = task[lo].p_first;
+    const uint32_t np = task[lo].np;
     const uint32_t E = 1u << a.log2e;
     const uint32_t emask = E - 1;
     constexpr uint32_t PB = kFillThreads * kFillPerThread;
-    const uint32_t pb = (uint32_t)(tile - T.tile_first);
+    const uint32_t pb = (uint32_t)(tile - t_first);
     for (uint32_t m = 0; m < kFillPerThread; ++m) {
         const uint32_t pi = pb * PB + threadIdx.x + m * kFillThreads;
-        if (pi >= T.np)
+        if (pi >= np)
             break;
-        const uint64_t idx = (uint64_t)T.p_first + pi;
+        const uint64_t idx = (uint64_t)p_first + pi;
         const uint32_t p = a.primes[idx];
         const double inv = gb_recip(p);
         const uint64_t p2 = (uint64_t)p * p;
         const uint32_t pm3 = p % 3;
-        for (uint32_t cc = 0; cc < T.nchunk; ++cc) {
-            const GbChunk &C = a.chunk[T.chunk_first + cc];
-            if (idx >= C.p_root)
+        for (uint32_t cc = 0; cc < c_n; ++cc) {
+            const uint32_t ci = c_first + cc;
+            if (idx >= chunk[ci].p_root)
                 continue;
+            const uint64_t Q0 = chunk[ci].Q0;
+            const uint64_t dmax = chunk[ci].dmax;
+            const uint64_t seg_first = chunk[ci].seg_first;
+            const uint32_t nseg = chunk[ci].nseg;
             // first odd multiple of p at or above max(Q0, p^2), as a window bit
-            const uint32_t r = gb_mod_u64_u32_inv(C.Q0, p, inv);
+            const uint32_t r = gb_mod_u64_u32_inv(Q0, p, inv);
             uint64_t x = r ? p - r : 0;
             if (x & 1)
                 x += p;                                          // Q0 is odd: x must be even
             uint64_t d = x >> 1;
-            if (p2 > C.Q0) {
-                const uint64_t dsq = (p2 - C.Q0) >> 1;
+            if (p2 > Q0) {
+                const uint64_t dsq = (p2 - Q0) >> 1;
                 if (dsq > d)
                     d = dsq;
             }
             // the odd number Q0 + 2d is a multiple of 3 when d = Q0 (mod 3):
             // the window keeps those bits clear, so they are not struck
-            const uint32_t q0m3 = (uint32_t)(C.Q0 % 3);
+            const uint32_t q0m3 = (uint32_t)(Q0 % 3);
             uint32_t dm3 = (uint32_t)(d % 3);
-            for (; d <= C.dmax; d += p) {
+            for (; d <= dmax; d += p) {
                 if (dm3 != q0m3) {
-                    const uint64_t s = d >> a.log2e;
+                    const uint64_t sg = d >> a.log2e;
                     const uint32_t off = (uint32_t)d & emask;
-                    if (s < C.nseg)
-                        strike(a, C.seg_first + s, off);
-                    if (off < a.H && s >= 1 && s - 1 < C.nseg)
-                        strike(a, C.seg_first + s - 1, off + E);
+                    if (sg < nseg)
+                        strike(a, seg_first + sg, off);
+                    if (off < a.H && sg >= 1 && sg - 1 < nseg)
+                        strike(a, seg_first + sg - 1, off + E);
                 }
                 dm3 += pm3;
                 dm3 = dm3 >= 3 ? dm3 - 3 : dm3;
