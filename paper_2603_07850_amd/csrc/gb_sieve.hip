@@ -57,6 +57,7 @@ struct CandGroup {
 typedef const __attribute__((address_space(4))) Cand *ccand_t;
 typedef const __attribute__((address_space(4))) CandGroup *cgroup_t;
 typedef const __attribute__((address_space(4))) uint32_t *cprime_t;
+typedef const __attribute__((address_space(4))) GbInterval *civ_t;
 
 // Test one candidate against a lane's 64 open evens (ul, uh; bit i: even
 // n0 + 128j + 2i): xl, xh hold the primality bits of the 64 numbers n - p,
@@ -385,19 +386,24 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
         const uint64_t seg = a.seg_base + claim;
 
         // ---- locate the interval and the segment geometry (uniform) ----
+        // (descriptors read through the constant address space: scalar loads)
+        const civ_t ivs = (civ_t)a.iv;
         uint32_t lo = 0, hi = a.k - 1;
         while (lo < hi) {
             const uint32_t mid = (lo + hi + 1) >> 1;
-            if (a.iv[mid].seg_first <= seg)
+            if (ivs[mid].seg_first <= seg)
                 lo = mid;
             else
                 hi = mid - 1;
         }
         const uint32_t ivx = lo;
-        const GbInterval I = a.iv[ivx];
-        const uint64_t js = seg - I.seg_first;
-        const uint64_t n0 = I.A + 2 * E * js;
-        const uint64_t rem = I.nE - E * js;
+        const uint64_t iv_seg_first = ivs[ivx].seg_first;
+        const uint64_t iv_A = ivs[ivx].A;
+        const uint64_t iv_nE = ivs[ivx].nE;
+        const uint64_t iv_nseg = ivs[ivx].nseg;
+        const uint64_t js = seg - iv_seg_first;
+        const uint64_t n0 = iv_A + 2 * E * js;
+        const uint64_t rem = iv_nE - E * js;
         const uint32_t cnt = (uint32_t)(rem < E ? rem : E);
         const uint32_t weff = cnt - 1 + H;          // odd bits [0, weff) are read by the probe
         const bool neg = n0 <= 2ull * H;            // q_lo < 0
@@ -727,7 +733,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
             a.rec[seg] = r;
             // the interval is complete when its last segment record is written
             __threadfence();
-            if (atomicAdd(&a.done[ivx].segs_done, 1ull) + 1 == I.nseg)
+            if (atomicAdd(&a.done[ivx].segs_done, 1ull) + 1 == iv_nseg)
                 a.done[ivx].t_done = wall_clock64();
         }
         __syncthreads();
