@@ -166,7 +166,7 @@ gb_status gb_get_params(gb_params *p);
 /*
  * Autotuner: time a calibration run of [A, B] (at most 2^36 evens) under each
  * segment size, workgroup size and probe window (and, when isqrt(B) > 2^22,
- * with and without bucket lists), keep the fastest as the current parameters
+ * with and without strike bitmaps), keep the fastest as the current parameters
  * and write it to *best (may be NULL).  Results of later calls do not depend
  * on the choice.
  */

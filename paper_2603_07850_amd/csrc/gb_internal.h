@@ -75,7 +75,7 @@ struct GbProbeArgs {
     GbCounters *ctr;
     unsigned long long *claim;  // this launch's segment queue head
     GbIvDone *done;
-    const uint32_t *bitmap;   // per segment (E + H)/32 words: bits struck by large
+    const uint32_t *bitmap;   // per segment 3 * wcu words (class layout): bits struck by large
                               // primes; null when the launch has no buckets
     const uint32_t *ctab;     // probe candidate tables, 3 words per entry (see below)
     const uint32_t *ptab;     // the candidate p of each table entry

@@ -135,7 +135,7 @@ struct Ctx {
     hipStream_t cap_stream = nullptr;   // capture stream of the batched graph
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uint64_t> graph_key;    // every value the captured sequence bakes in
-    // bucket lists of the large primes
+    // strike bitmaps of the large primes, their chunks and fill tasks
     DevBuf d_bitmap, d_chunk, d_claims, d_task;
     HostBuf h_chunk, h_task;
     std::vector<uint64_t> last_slot;    // last call: caller's index -> kernel slot

@@ -5,8 +5,8 @@
 // probe every even n of the segment against the ascending candidate primes
 // (Phase 1, Sec. 3.3).
 //
-// Geometry of one segment (E = 2^LOG2E evens, halo H bits, window W = E + H
-// bits of LDS):
+// Geometry of one segment (E = 2^LOG2E evens, halo H odd bits, H a multiple
+// of 96, window W = E + H odd numbers):
 //   evens    n = n0 + 2i, 0 <= i < cnt <= E
 //   bit b    odd q = q_lo + 2b,  q_lo = n0 - 1 - 2H   (q_lo may be negative
 //            for the first segments; every q <= 1 is marked composite)
@@ -16,24 +16,33 @@
 // windows overlap by H bits and a window bit d of the interval belongs to
 // segment d >> LOG2E (and to the previous one when d mod E < H).
 //
+// LDS layout: odd bit b is bit b / 3 of class array b mod 3.  The class t3
+// with q_lo + 2*t3 = 0 (mod 3) holds exactly the odd multiples of 3 and is
+// not stored; the other two classes are LDS slots 0 and 1.
+//
 // Sieve (every q is odd):
-//   * primes 3..31   periodic 32-bit word masks, one word write per 32 odds;
+//   * primes 5..31   periodic 32-bit word masks per class, one word write per
+//                    32 class bits;
 //   * primes >= 37   strided clears from max(p^2, first multiple in the
-//                    window) with LDS atomic AND; primes up to E/1024 are
-//                    cleared by one wave each (each lane keeps one bit
-//                    position, so its mask is loop-invariant), larger ones one
-//                    prime per thread with several table loads in flight;
+//                    window) with LDS atomic AND, class by class (a prime's
+//                    multiples in one class are p class bits apart); primes up
+//                    to E/512 are cleared by one wave each (each lane keeps one
+//                    bit position, so its mask is loop-invariant), larger ones
+//                    one prime per thread with several table loads in flight;
 //   * primes above the bucket bound (when the launch has buckets) are not
 //                    visited here: the bucket-fill kernel has set the window
 //                    bits they strike in the segment's strike bitmap in HBM,
 //                    which the presieve folds into the LDS window.
-// Probe (bit-parallel): a thread owns 64 consecutive evens.  For candidate p
-// the 64 bits q = n - p of those evens are 64 consecutive window bits, so two
-// funnel shifts of three LDS words test p against all 64 evens at once; hits are
-// removed from the thread's unresolved mask and the wave stops when no lane
-// has an unresolved even left.  Ascending p makes the first hit the minimal
-// one.  Evens still open after the window are appended to the spill list for
-// the Phase-2 kernel.
+// Probe (bit-parallel): evens of one residue class r (n = n0 + 2r + 6i') go
+// to a wave together, a lane owning 64 consecutive i'.  For candidate p the 64
+// bits q = n - p of those evens are 64 consecutive bits of one class array, so
+// two funnel shifts of three LDS words test p against all 64 evens at once;
+// candidates whose n - p falls in class t3 are skipped.  Hits are removed
+// from the lane's open masks and the wave stops when no lane has an open even
+// left; ascending p makes the first hit the minimal one.  A first pass gives
+// every block a fixed number of candidates, a second pass finishes the few
+// still-open blocks packed 64 per wave.  Evens still open after the window
+// are appended to the spill list for the Phase-2 kernel.
 #include "gb_arith.h"
 #include "gb_internal.h"
 

@@ -252,8 +252,8 @@ BUCKET_CASES = [
 
 @pytest.mark.parametrize("blog", [17, 19, 0])
 @pytest.mark.parametrize("mib", [0, 1])
-def test_bucket_lists_parity(gb, O, blog, mib):
-    """Primes above the bucket bound cleared from bucket lists: identical to the
+def test_strike_bitmaps_parity(gb, O, blog, mib):
+    """Primes above the bucket bound cleared through strike bitmaps: identical to the
     oracle, with one or many rounds (a 1 MiB budget splits ranges into many
     chunks and rounds)."""
     saved = gb.get_params()
@@ -265,7 +265,7 @@ def test_bucket_lists_parity(gb, O, blog, mib):
         gb.set_params(**saved)
 
 
-def test_bucket_batch_equals_single(gb, O):
+def test_strike_bitmap_batch_equals_single(gb, O):
     table(gb, 2**32 - 1)
     saved = gb.get_params()
     try:
