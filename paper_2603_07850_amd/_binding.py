@@ -174,21 +174,24 @@ def verify_range(A, B, P_max, stream=None, unresolved_cap=1 << 16, allow_trunc=T
 
 def verify_batch(intervals, P_max, stream=None, unresolved_cap=1024, allow_trunc=True):
     """Verify k intervals [(A, B), ...] in one persistent launch; list of dicts."""
+    import numpy as np
     k = len(intervals)
     AB = (ctypes.c_uint64 * (2 * max(k, 1)))()
-    for i, (a, b) in enumerate(intervals):
-        AB[2 * i] = int(a)
-        AB[2 * i + 1] = int(b)
+    AB[0:2 * k] = [int(x) for ab in intervals for x in ab]
     outs = (Result * max(k, 1))()
-    bufs = []
-    for i in range(k):
-        b = (ctypes.c_uint64 * max(int(unresolved_cap), 1))()
-        bufs.append(b)
-        outs[i].unresolved = ctypes.cast(b, ctypes.POINTER(ctypes.c_uint64))
-        outs[i].unresolved_cap = int(unresolved_cap)
+    cap = max(int(unresolved_cap), 1)
+    pool = np.empty(cap * max(k, 1), dtype=np.uint64)   # one buffer, a slice per interval
+    # the gb_result array seen as rows of 11 u64 (the pointer is the 10th)
+    view = np.frombuffer(outs, dtype=np.uint64).reshape(max(k, 1), 11)
+    view[:, 9] = pool.ctypes.data + np.arange(max(k, 1), dtype=np.uint64) * (cap * 8)
+    view[:, 10] = int(unresolved_cap)
     st = lib().gb_verify_batch(AB, k, int(P_max), _stream(stream), outs)
     _check(st, ok=(0, 5) if allow_trunc else (0,))
-    return [_to_dict(outs[i], bufs[i]) for i in range(k)]
+    res = [dict(zip(RESULT_FIELDS, row)) for row in view[:k, :9].tolist()]
+    for i, d in enumerate(res):
+        n = min(d["n_unresolved"], int(unresolved_cap))
+        d["unresolved"] = pool[i * cap:i * cap + n].tolist() if n else []
+    return res
 
 
 def set_params(seg_log2=18, wg_size=256, window=4096, wg_per_cu=0, bucket_log2=0, bucket_mib=0):
