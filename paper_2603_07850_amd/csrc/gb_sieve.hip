@@ -18,13 +18,15 @@
 //
 // LDS layout: odd bit b is bit b / 3 of class array b mod 3.  The class t3
 // with q_lo + 2*t3 = 0 (mod 3) holds exactly the odd multiples of 3 and is
-// not stored; the other two classes are LDS slots 0 and 1.
+// not stored; the other two classes are LDS slots 0 and 1.  A bit is a strike
+// mark: 1 = struck (not prime), 0 = prime, the convention of the strike
+// bitmaps in HBM, so a strike is one OR.
 //
 // Sieve (every q is odd):
 //   * primes 5..31   periodic 32-bit word masks per class, one word write per
 //                    32 class bits;
-//   * primes >= 37   strided clears from max(p^2, first multiple in the
-//                    window) with LDS atomic AND, class by class (a prime's
+//   * primes >= 37   strikes from max(p^2, first multiple in the window) with
+//                    LDS atomic OR, class by class (a prime's
 //                    multiples in one class are p class bits apart); primes up
 //                    to E/512 are cleared by one wave each (each lane keeps one
 //                    bit position, so its mask is loop-invariant), larger ones
@@ -69,8 +71,9 @@ typedef const __attribute__((address_space(4))) uint32_t *cprime_t;
 typedef const __attribute__((address_space(4))) GbInterval *civ_t;
 
 // Test one candidate against a lane's 64 open evens (ul, uh; bit i: even
-// n0 + 128j + 2i): xl, xh hold the primality bits of the 64 numbers n - p,
-// funnel-shifted out of three LDS words; the hits leave the open masks.
+// n0 + 128j + 2i): xl, xh hold the strike bits of the 64 numbers n - p
+// (1 = not prime), funnel-shifted out of three LDS words; an even stays open
+// only where n - p is struck.
 __device__ __forceinline__ void probe_one(const char *lds, uint32_t base4, uint32_t off,
                                           uint32_t sh, uint32_t gap, uint32_t &ul, uint32_t &uh,
                                           uint32_t &acc)
@@ -82,8 +85,8 @@ __device__ __forceinline__ void probe_one(const char *lds, uint32_t base4, uint3
     const uint32_t xl = __builtin_amdgcn_alignbit(w1, w0, sh);
     const uint32_t xh = __builtin_amdgcn_alignbit(w2, w1, sh);
     acc = __umul24(gap, (uint32_t)(__popc(ul) + __popc(uh))) + acc;
-    ul &= ~xl;
-    uh &= ~xh;
+    ul &= xl;
+    uh &= xh;
 }
 
 __device__ __forceinline__ void probe_group(const char *lds, uint32_t base4, cgroup_t G,
@@ -146,12 +149,10 @@ __device__ __forceinline__ uint32_t first_bit(uint64_t qlo, uint64_t qneg, bool 
 }
 
 // First window bit as above for a window start 0 < q_lo < 2^52, which a
-// double holds exactly (qd = q_lo, qlo32 = its low word, sq = isqrt(q_lo)),
-// and p < 2^26: one double quotient estimate, within one of floor(q_lo / p),
-// and an exact fma remainder in (-p, 2p) that one step corrects.  When
-// p > sq, p^2 lies past q_lo by less than the window, so the distance fits
-// 32 bits.
-__device__ __forceinline__ uint32_t first_bit_d(double qd, uint32_t qlo32, uint32_t sq, uint32_t p)
+// double holds exactly (qd = q_lo), and p < 2^26: one double quotient
+// estimate, within one of floor(q_lo / p), and an exact fma remainder in
+// (-p, 2p) that one step corrects.
+__device__ __forceinline__ uint32_t first_bit_d(double qd, uint32_t p)
 {
     const double pd = (double)p;
     double inv = __builtin_amdgcn_rcp(pd);
@@ -165,8 +166,11 @@ __device__ __forceinline__ uint32_t first_bit_d(double qd, uint32_t qlo32, uint3
     r -= r >= (int32_t)p ? (int32_t)p : 0;
     const uint32_t x = r ? p - (uint32_t)r : 0u;  // -q_lo mod p
     uint32_t j = (x & 1) ? (x >> 1) + (p >> 1) + 1 : (x >> 1);
-    const uint32_t jsq = (p * p - qlo32) >> 1;
-    return (p > sq && jsq > j) ? jsq : j;
+    // bit of p^2 when it lies past q_lo: p^2 - q_lo is exact in double (both
+    // terms below 2^52, an even integer), clamped to [0, 2^33 - 2]
+    const double dsq = __builtin_fmin(__builtin_fmax(__builtin_fma(pd, pd, -qd), 0.0), 8589934590.0);
+    const uint32_t jsq = (uint32_t)(dsq * 0.5);
+    return jsq > j ? jsq : j;
 }
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t v)
@@ -189,33 +193,88 @@ __device__ __forceinline__ uint32_t count_le(const uint32_t *primes, uint64_t np
     return (uint32_t)lo;
 }
 
-// Clear the odd bits j, j + p, ... below weff (one prime, one thread) in the
-// class arrays of the window; class t3 (multiples of 3) is not stored.  A
-// prime below the window strikes many bits: its multiples in each of the two
-// other classes t are the class indices i_t, i_t + p, ..., so each class gets
-// a plain strided loop.  A larger prime strikes at most once.
+// floor(x / 3) for x < 2^23 in single precision (full-rate conversions and
+// multiply; a 32-bit high multiply is quarter rate).  The float nearest 1/3
+// exceeds it by less than 1e-8, so x times it lies in [x/3, x/3 + 0.09) and
+// its rounding (half an ulp, at most 1/8 below 2^22) keeps the product in
+// [floor(x/3), floor(x/3) + 1): truncation gives the quotient.
+__device__ __forceinline__ uint32_t div3(uint32_t x)
+{
+    return (uint32_t)((float)x * (1.0f / 3.0f));
+}
+
+// x mod 3 given q = floor(x / 3) < 2^23: one 24-bit multiply-add (the empty
+// asm keeps the compiler from merging it into a 64-bit multiply-add).
+__device__ __forceinline__ uint32_t mod3(uint32_t x, uint32_t q)
+{
+    uint32_t r = (uint32_t)__mul24((int32_t)q, -3) + x;
+    asm("" : "+v"(r));
+    return r;
+}
+
+// The multiples j + k*p (p prime to 3) run through the three classes as k
+// does mod 3; the one in class t is k = (t - j) * p mod 3 (p is its own
+// inverse mod 3).  kt_table(t) holds that k for every (j mod 3, p mod 3) as
+// 2-bit fields at bit 2 * (j mod 3) + 6 * (p mod 3).
+__host__ __device__ constexpr uint32_t kt_table(uint32_t t)
+{
+    uint32_t K = 0;
+    for (uint32_t jm = 0; jm < 3; ++jm)
+        for (uint32_t pm = 1; pm < 3; ++pm)
+            K |= (((t + 3 - jm) * pm) % 3) << (2 * jm + 6 * pm);
+    return K;
+}
+
+// Uniform class geometry of one window: the class kept in slot 0 (slot 1
+// holds the other one that is not t3), the class indices of each slot inside
+// the window, and each slot's kt_table.
+struct ClassGeo {
+    uint32_t t3, tA;
+    uint32_t lim[2];
+    uint32_t ktab[2];
+};
+
+__device__ __forceinline__ ClassGeo class_geo(uint32_t t3, uint32_t weff)
+{
+    constexpr uint32_t K0 = kt_table(0), K1 = kt_table(1), K2 = kt_table(2);
+    ClassGeo g;
+    g.t3 = t3;
+    g.tA = t3 == 2 ? 0u : t3 + 1;
+    const uint32_t tB = t3 == 0 ? 2u : t3 - 1;
+    g.lim[0] = (weff + 2 - g.tA) / 3;
+    g.lim[1] = (weff + 2 - tB) / 3;
+    g.ktab[0] = g.tA == 0 ? K0 : (g.tA == 1 ? K1 : K2);
+    g.ktab[1] = tB == 0 ? K0 : (tB == 1 ? K1 : K2);
+    return g;
+}
+
+// Strike the odd bits j, j + p, ... below weff (one prime, one thread) in the
+// class arrays of the window.  A prime below the window strikes many bits:
+// its multiples in one stored class are the class indices i, i + p, ..., one
+// strided loop per class.  A larger prime strikes at most once.
 template <uint32_t WC>
-__device__ __forceinline__ void strike_prime(uint32_t *bits, uint32_t weff, uint32_t t3, uint32_t p,
-                                             uint32_t j)
+__device__ __forceinline__ void strike_prime(uint32_t *bits, const ClassGeo &g, uint32_t weff,
+                                             uint32_t p, uint32_t j)
 {
     if (j >= weff)
         return;
     if (p < weff) {
-        const uint32_t jm = j % 3, pm = p % 3;
-        for (uint32_t s2 = 1; s2 <= 2; ++s2) {
-            const uint32_t t = (t3 + s2) % 3;
-            const uint32_t kt = ((t + 3 - jm) * pm) % 3;  // j + kt*p = t (mod 3)
-            const uint32_t bt = j + kt * p;
-            uint32_t *cw = bits + (s2 - 1) * WC;             // class t is kept in slot s2 - 1
-            const uint32_t lim = (weff + 2 - t) / 3;       // class indices in the window
-            for (uint32_t i = (bt - t) / 3; i < lim; i += p)
-                atomicAnd(&cw[i >> 5], ~(1u << (i & 31)));
+        // here j, p < weff < 2^21, so j + 2p < 2^23
+        const uint32_t jm = mod3(j, div3(j));
+        const uint32_t pm = mod3(p, div3(p));
+        const uint32_t sh = 2 * jm + __umul24(pm, 6u);
+#pragma unroll
+        for (uint32_t s = 0; s < 2; ++s) {
+            const uint32_t kt = (g.ktab[s] >> sh) & 3u;
+            uint32_t *cw = bits + s * WC;
+            for (uint32_t i = div3(j + __umul24(kt, p)); i < g.lim[s]; i += p)
+                atomicOr(&cw[i >> 5], 1u << (i & 31));
         }
     } else {
-        const uint32_t i = __umulhi(j, 0xAAAAAAABu) >> 1;  // j / 3
-        const uint32_t t = j - 3 * i;
-        if (t != t3)
-            atomicAnd(&bits[__umul24((t + 2 - t3) % 3, WC) + (i >> 5)], ~(1u << (i & 31)));
+        const uint32_t i = div3(j);
+        const uint32_t t = mod3(j, i);
+        if (t != g.t3)
+            atomicOr(&bits[(t == g.tA ? 0u : WC) + (i >> 5)], 1u << (i & 31));
     }
 }
 
@@ -299,8 +358,8 @@ __device__ __forceinline__ void finish_block(const GbProbeArgs &a, const char *l
             const uint32_t w0 = *(const uint32_t *)(lds + addr);
             const uint32_t w1 = *(const uint32_t *)(lds + addr + 4);
             const uint32_t w2 = *(const uint32_t *)(lds + addr + 8);
-            const uint32_t xl = __builtin_amdgcn_alignbit(w1, w0, e[1]) & vl;
-            const uint32_t xh = __builtin_amdgcn_alignbit(w2, w1, e[1]) & vh;
+            const uint32_t xl = ~__builtin_amdgcn_alignbit(w1, w0, e[1]) & vl;
+            const uint32_t xh = ~__builtin_amdgcn_alignbit(w2, w1, e[1]) & vh;
             if (xl | xh) {
                 vl ^= xl;
                 vh ^= xh;
@@ -425,7 +484,6 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
         // windows starting in (0, 2^52) take the double-precision first-bit path
         const bool small = !neg && qlo < (1ull << 52);
         const double qd = (double)qlo;
-        const uint32_t sq = small ? gb_isqrt64(qlo) : 0u;
         if (wave == 0) {
             const uint32_t c = count_le_wave(primes, a.nprimes, gb_isqrt64(qhi), lane);
             if (lane == 0)
@@ -470,7 +528,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                         m |= word_pattern(kPre[i + 1]) << ph[i];
                         ph[i] = ph[i] >= dec[i] ? ph[i] - dec[i] : ph[i] + kPre[i + 1] - dec[i];
                     }
-                    cw[w] = ~m;
+                    cw[w] = m;
                 }
             }
         }
@@ -488,7 +546,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                         if (b > bmax)
                             break;
                         const int64_t q = neg ? (int64_t)(2 * b) - (int64_t)qneg : (int64_t)(qlo + 2 * b);
-                        v = small_prime_35(q) ? (v | (1u << k)) : (v & ~(1u << k));
+                        v = small_prime_35(q) ? (v & ~(1u << k)) : (v | (1u << k));
                     }
                     bits[sl * WC + w] = v;
                 }
@@ -499,34 +557,36 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
         const uint32_t nroot = __builtin_amdgcn_readfirstlane(sh_nroot);  // published by the barrier above
         const uint32_t nsieve = nroot < a.lb_count ? nroot : a.lb_count;  // primes cleared here
 
-        // ---- strided clears, one prime per wave: 37 <= p <= kWaveTierMax ----
-        // The prime's odd multiples b = j0 + kp fall in the two classes other
-        // than t3 at class indices i_t + mp.  Lane l strikes i_t + l*p + m*64p;
+        // ---- strikes, one prime per wave: 37 <= p <= kWaveTierMax ----
+        // The prime's odd multiples b = j0 + kp fall in the two stored
+        // classes at class indices i_s + mp.  Lane l strikes i_s + l*p + m*64p;
         // 64p is a multiple of 32, so a lane's bit position and mask never change.
+        const ClassGeo cg = class_geo(t3, weff);
         {
             const uint32_t wave_end = nwave < nsieve ? nwave : nsieve;
             for (uint32_t i = kFirstStrided + wv; i < wave_end; i += NWAVE) {
                 const uint32_t p = cp[i];
-                const uint32_t j0 = small ? first_bit_d(qd, (uint32_t)qlo, sq, p)
+                const uint32_t j0 = small ? first_bit_d(qd, p)
                                           : first_bit(qlo, qneg, neg, p);
-                const uint32_t pm = p % 3, jm = j0 % 3;
-                for (uint32_t s2 = 1; s2 <= 2; ++s2) {
-                    const uint32_t t = (t3 + s2) % 3;
-                    const uint32_t kt = ((t + 3 - jm) * pm) % 3;   // j0 + kt*p = t (mod 3)
-                    const uint64_t bt = (uint64_t)j0 + (uint64_t)kt * p;
-                    const uint32_t lim = (weff + 2 - t) / 3;        // class indices in the window
-                    const uint64_t it = (bt - t) / 3 + (uint64_t)lane * p;
-                    if (bt < weff && it < lim) {
-                        const uint32_t mask = ~(1u << (it & 31));
-                        const uint32_t wend = (lim + 31) >> 5;
-                        uint32_t *cw = bits + (s2 - 1) * WC;
-                        for (uint32_t w = (uint32_t)(it >> 5); w < wend; w += 2 * p)
-                            atomicAnd(&cw[w], mask);
+                if (j0 >= weff)
+                    continue;
+                // j0 < weff < 2^21 and p <= 2^11: j0 + 2p < 2^23
+                const uint32_t sh = 2 * mod3(j0, div3(j0)) + __umul24(mod3(p, div3(p)), 6u);
+#pragma unroll
+                for (uint32_t sl = 0; sl < 2; ++sl) {
+                    const uint32_t kt = (cg.ktab[sl] >> sh) & 3u;
+                    const uint32_t it = div3(j0 + __umul24(kt, p)) + __umul24(lane, p);
+                    if (it < cg.lim[sl]) {
+                        const uint32_t mask = 1u << (it & 31);
+                        const uint32_t wend = (cg.lim[sl] + 31) >> 5;
+                        uint32_t *cw = bits + sl * WC;
+                        for (uint32_t w = it >> 5; w < wend; w += 2 * p)
+                            atomicOr(&cw[w], mask);
                     }
                 }
             }
         }
-        // ---- strided clears, one prime per thread: kWaveTierMax < p <= min(isqrt(q_hi), bound) ----
+        // ---- strikes, one prime per thread: kWaveTierMax < p <= min(isqrt(q_hi), bound) ----
         // kPrimesInFlight table loads are issued before the first is used.
         {
             const uint32_t first = nwave > kFirstStrided ? nwave : kFirstStrided;
@@ -541,13 +601,13 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
 #pragma unroll
                     for (uint32_t t = 0; t < kPrimesInFlight; ++t)
                         if (pv[t])
-                            strike_prime<WC>(bits, weff, t3, pv[t],
-                                             first_bit_d(qd, (uint32_t)qlo, sq, pv[t]));
+                            strike_prime<WC>(bits, cg, weff, pv[t],
+                                             first_bit_d(qd, pv[t]));
                 } else {
 #pragma unroll
                     for (uint32_t t = 0; t < kPrimesInFlight; ++t)
                         if (pv[t])
-                            strike_prime<WC>(bits, weff, t3, pv[t], first_bit(qlo, qneg, neg, pv[t]));
+                            strike_prime<WC>(bits, cg, weff, pv[t], first_bit(qlo, qneg, neg, pv[t]));
                 }
             }
         }
