@@ -20,7 +20,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/goldbach.h"
+#include "goldbach.h"
 #include "gb_internal.h"
 
 namespace {

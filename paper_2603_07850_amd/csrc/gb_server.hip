@@ -27,7 +27,7 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/goldbach.h"
+#include "goldbach.h"
 #include "gb_internal.h"
 
 namespace {

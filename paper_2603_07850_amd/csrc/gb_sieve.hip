@@ -398,11 +398,34 @@ constexpr uint32_t gb_probe_queue(int log2e)
     return 1u << (log2e - 10);
 }
 
+// Number of primes in [37, x], counted at compile time (x <= 2^11 here).
+constexpr uint32_t primes_from_37(uint32_t x)
+{
+    uint32_t c = 0;
+    for (uint32_t n = 37; n <= x; n += 2) {
+        bool pr = true;
+        for (uint32_t d = 3; d * d <= n; d += 2)
+            if (n % d == 0) {
+                pr = false;
+                break;
+            }
+        c += pr ? 1u : 0u;
+    }
+    return c;
+}
+
+// Primes up to this bound strike a window at least 1024 times: one wave each.
+constexpr uint32_t wave_tier_max(int log2e)
+{
+    return 1u << (log2e - 9);
+}
+
 // Waves per SIMD that the LDS window allows (160 KB of LDS per CU, four SIMDs,
 // at most eight waves each): the register budget is set to match it.
 constexpr uint32_t lds_waves_per_simd(int log2e, int nt)
 {
-    const uint32_t wg_bytes = 2 * 4 * gb_class_words(log2e) + 30 * gb_probe_queue(log2e) + 1024;
+    const uint32_t wg_bytes = 2 * 4 * gb_class_words(log2e) + 30 * gb_probe_queue(log2e) +
+                              8 * primes_from_37(wave_tier_max(log2e)) + 1024;
     const uint32_t wgs = (160u * 1024u) / wg_bytes;
     const uint32_t w = wgs * (uint32_t)(nt / 64) / 4;
     return w < 1 ? 1 : (w > 8 ? 8 : w);
@@ -415,8 +438,8 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
     constexpr uint64_t E = 1ull << LOG2E;
     constexpr uint32_t WC = gb_class_words(LOG2E);  // words per class array
     constexpr uint32_t NWAVE = NT / 64;
-    // primes up to this bound strike a window >= 1024 times: one wave each
-    constexpr uint32_t kWaveTierMax = (uint32_t)(E >> 9);
+    constexpr uint32_t kWaveTierMax = wave_tier_max(LOG2E);
+    constexpr uint32_t kWaveN = primes_from_37(kWaveTierMax);
     __shared__ uint32_t bits[2 * WC];   // classes t3 + 1 and t3 + 2 (mod 3)
     // second-pass queues, one per class of evens: block index and open masks
     constexpr uint32_t kQueue = gb_probe_queue(LOG2E);
@@ -424,6 +447,8 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
     __shared__ uint32_t ql[3][kQueue];
     __shared__ uint32_t qh[3][kQueue];
     __shared__ uint32_t qn[3];
+    // first class index of each wave-tier prime in the two stored classes
+    __shared__ uint32_t wt_i[2][kWaveN];
     __shared__ unsigned long long sh_seg;
     __shared__ uint32_t sh_nroot;
     __shared__ unsigned long long red_sum[NWAVE];
@@ -444,14 +469,18 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
     const uint32_t nwave = count_le(primes, a.nprimes, kWaveTierMax);
     const uint32_t tabbase = (uint32_t)(LOG2E - 18) * 9;
 
+    if (tid == 0)
+        sh_seg = atomicAdd(a.claim, 1ull);
+    __syncthreads();
     for (;;) {
-        if (tid == 0)
-            sh_seg = atomicAdd(a.claim, 1ull);
-        __syncthreads();
-        const uint64_t claim = uniform64(sh_seg);
+        const uint64_t claim = uniform64(sh_seg);  // published by the last barrier
         if (claim >= a.nsegs)
             break;
         const uint64_t seg = a.seg_base + claim;
+        // the next claim is taken now: its round trip overlaps this segment
+        unsigned long long next_claim = 0;
+        if (tid == 0)
+            next_claim = atomicAdd(a.claim, 1ull);
 
         // ---- locate the interval and the segment geometry (uniform) ----
         // (descriptors read through the constant address space: scalar loads)
@@ -481,6 +510,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
         // class of the multiples of 3: q_lo + 2*t3 = 0 (mod 3)
         const uint32_t x3 = neg ? (uint32_t)(qneg % 3) : (uint32_t)((3 - qlo % 3) % 3);
         const uint32_t t3 = (2 * x3) % 3;
+        const ClassGeo cg = class_geo(t3, weff);
         // windows starting in (0, 2^52) take the double-precision first-bit path
         const bool small = !neg && qlo < (1ull << 52);
         const double qd = (double)qlo;
@@ -490,6 +520,24 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                 sh_nroot = c;
         }
 
+        // first class indices of the wave-tier primes, one prime per thread
+        // (published, like qn, by the barrier after the presieve)
+        {
+            const uint32_t nw = nwave - kFirstStrided < kWaveN ? nwave - kFirstStrided : kWaveN;
+            for (uint32_t t = tid; t < nw; t += NT) {
+                const uint32_t p = primes[kFirstStrided + t];
+                const uint32_t j0 = small ? first_bit_d(qd, p) : first_bit(qlo, qneg, neg, p);
+                uint32_t i0 = 0xFFFFFFFFu, i1 = 0xFFFFFFFFu;
+                if (j0 < weff) {
+                    // j0 < weff < 2^21 and p <= 2^11: j0 + 2p < 2^23
+                    const uint32_t sh = 2 * mod3(j0, div3(j0)) + __umul24(mod3(p, div3(p)), 6u);
+                    i0 = div3(j0 + __umul24((cg.ktab[0] >> sh) & 3u, p));
+                    i1 = div3(j0 + __umul24((cg.ktab[1] >> sh) & 3u, p));
+                }
+                wt_i[0][t] = i0;
+                wt_i[1][t] = i1;
+            }
+        }
         if (tid < 3)
             qn[tid] = 0;   // published by the barrier after the presieve
         // ---- presieve: periodic masks of 5..31 in the two stored classes ----
@@ -561,21 +609,16 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
         // The prime's odd multiples b = j0 + kp fall in the two stored
         // classes at class indices i_s + mp.  Lane l strikes i_s + l*p + m*64p;
         // 64p is a multiple of 32, so a lane's bit position and mask never change.
-        const ClassGeo cg = class_geo(t3, weff);
         {
             const uint32_t wave_end = nwave < nsieve ? nwave : nsieve;
             for (uint32_t i = kFirstStrided + wv; i < wave_end; i += NWAVE) {
                 const uint32_t p = cp[i];
-                const uint32_t j0 = small ? first_bit_d(qd, p)
-                                          : first_bit(qlo, qneg, neg, p);
-                if (j0 >= weff)
-                    continue;
-                // j0 < weff < 2^21 and p <= 2^11: j0 + 2p < 2^23
-                const uint32_t sh = 2 * mod3(j0, div3(j0)) + __umul24(mod3(p, div3(p)), 6u);
 #pragma unroll
                 for (uint32_t sl = 0; sl < 2; ++sl) {
-                    const uint32_t kt = (cg.ktab[sl] >> sh) & 3u;
-                    const uint32_t it = div3(j0 + __umul24(kt, p)) + __umul24(lane, p);
+                    const uint32_t i0 = __builtin_amdgcn_readfirstlane(wt_i[sl][i - kFirstStrided]);
+                    if (i0 >= cg.lim[sl])
+                        continue;
+                    const uint32_t it = i0 + __umul24(lane, p);
                     if (it < cg.lim[sl]) {
                         const uint32_t mask = 1u << (it & 31);
                         const uint32_t wend = (cg.lim[sl] + 31) >> 5;
@@ -782,6 +825,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
             red_n[wave] = bestn;
         }
         __syncthreads();
+        GbSegRecord rec;
         if (tid == 0) {
             uint64_t s = 0, c = 0, bn = 0;
             uint32_t bp = 0;
@@ -793,19 +837,23 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                     bn = red_n[w];
                 }
             }
-            GbSegRecord r;
-            r.checksum = s;
-            r.verified = c;
-            r.max_p = bp;
-            r.max_n = bp ? bn : 0;
-            r.pad = 0;
-            a.rec[seg] = r;
-            // the interval is complete when its last segment record is written
+            rec.checksum = s;
+            rec.verified = c;
+            rec.max_p = bp;
+            rec.max_n = bp ? bn : 0;
+            rec.pad = 0;
+            sh_seg = next_claim;
+        }
+        __syncthreads();
+        // the record is written after the barrier, so the other waves start
+        // the next segment while this one waits on the fence; the interval
+        // is complete when its last segment record is written
+        if (tid == 0) {
+            a.rec[seg] = rec;
             __threadfence();
             if (atomicAdd(&a.done[ivx].segs_done, 1ull) + 1 == iv_nseg)
                 a.done[ivx].t_done = wall_clock64();
         }
-        __syncthreads();
     }
 }
 
