@@ -477,10 +477,6 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
         if (claim >= a.nsegs)
             break;
         const uint64_t seg = a.seg_base + claim;
-        // the next claim is taken now: its round trip overlaps this segment
-        unsigned long long next_claim = 0;
-        if (tid == 0)
-            next_claim = atomicAdd(a.claim, 1ull);
 
         // ---- locate the interval and the segment geometry (uniform) ----
         // (descriptors read through the constant address space: scalar loads)
@@ -768,6 +764,12 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
             finish_block(a, lds, base4, tab, nv, k, ul, uh, acc, lastg, gl, gh, open0 - qopen,
                          n0 + 2ull * r + 384ull * m, ivx, sum, nres, bestp, bestn);
         }
+        // The next segment is claimed here by the last wave, which takes no
+        // more first-pass blocks than wave 0 and so can wait on the round
+        // trip; sh_seg was read by every thread before the barriers above and
+        // is read again after the one that ends this pass of the loop.
+        if (tid == NT - 64)
+            sh_seg = atomicAdd(a.claim, 1ull);
         __syncthreads();
         // second pass over the queued blocks, 64 per wave, class by class
         {
@@ -842,7 +844,6 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
             rec.max_p = bp;
             rec.max_n = bp ? bn : 0;
             rec.pad = 0;
-            sh_seg = next_claim;
         }
         __syncthreads();
         // the record is written after the barrier, so the other waves start
