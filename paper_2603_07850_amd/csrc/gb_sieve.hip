@@ -70,13 +70,20 @@ typedef const __attribute__((address_space(4))) CandGroup *cgroup_t;
 typedef const __attribute__((address_space(4))) uint32_t *cprime_t;
 typedef const __attribute__((address_space(4))) GbInterval *civ_t;
 
+// Open evens of a lane's block.
+__device__ __forceinline__ uint32_t open_count(uint32_t ul, uint32_t uh)
+{
+    return (uint32_t)(__popc(ul) + __popc(uh));
+}
+
 // Test one candidate against a lane's 64 open evens (ul, uh; bit i: even
 // n0 + 128j + 2i): xl, xh hold the strike bits of the 64 numbers n - p
 // (1 = not prime), funnel-shifted out of three LDS words; an even stays open
-// only where n - p is struck.
+// only where n - p is struck.  c is the lane's open count before the entry
+// (the gap-form checksum term).
 __device__ __forceinline__ void probe_one(const char *lds, uint32_t base4, uint32_t off,
-                                          uint32_t sh, uint32_t gap, uint32_t &ul, uint32_t &uh,
-                                          uint32_t &acc)
+                                          uint32_t sh, uint32_t gap, uint32_t c, uint32_t &ul,
+                                          uint32_t &uh, uint32_t &acc)
 {
     const uint32_t addr = base4 - off;
     const uint32_t w0 = *(const uint32_t *)(lds + addr);
@@ -84,24 +91,43 @@ __device__ __forceinline__ void probe_one(const char *lds, uint32_t base4, uint3
     const uint32_t w2 = *(const uint32_t *)(lds + addr + 8);
     const uint32_t xl = __builtin_amdgcn_alignbit(w1, w0, sh);
     const uint32_t xh = __builtin_amdgcn_alignbit(w2, w1, sh);
-    acc = __umul24(gap, (uint32_t)(__popc(ul) + __popc(uh))) + acc;
+    acc = __umul24(gap, c) + acc;
     ul &= xl;
     uh &= xh;
 }
 
-__device__ __forceinline__ void probe_group(const char *lds, uint32_t base4, cgroup_t G,
-                                            uint32_t k, uint32_t &ul, uint32_t &uh,
-                                            uint32_t &acc, uint32_t &lastg, uint32_t &gl,
-                                            uint32_t &gh)
+// Four entries; c is the open count before the first.
+__device__ __forceinline__ void probe_group(const char *lds, uint32_t base4, cgroup_t G, uint32_t c,
+                                            uint32_t &ul, uint32_t &uh, uint32_t &acc)
 {
-    const uint32_t sl = ul, sh = uh;
+    probe_one(lds, base4, G->c[0].off, G->c[0].sh, G->c[0].gap, c, ul, uh, acc);
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-        probe_one(lds, base4, G->c[t].off, G->c[t].sh, G->c[t].gap, ul, uh, acc);
-    const bool any = (ul != sl) | (uh != sh);
-    lastg = any ? k : lastg;
-    gl = any ? sl : gl;
-    gh = any ? sh : gh;
+    for (int t = 1; t < 4; ++t)
+        probe_one(lds, base4, G->c[t].off, G->c[t].sh, G->c[t].gap, open_count(ul, uh), ul, uh,
+                  acc);
+}
+
+// State of the group loop of one probe pass: the wave's last group with a
+// hit (lastk, uniform: its first entry, 0 if none) and the lane's open masks
+// at its start (gl, gh), plus the first entry pk (uniform, 0: none) of the
+// group just run.  That group's start masks and count live in one of two
+// register sets that the loop uses in turn, so no copy is made per group.
+struct ProbeTrack {
+    uint32_t lastk, gl, gh, pk;
+};
+
+// Settle the group just run, whose start state is (tl, th, pc): it hit
+// somewhere in the wave iff some lane's open count fell below pc.  c is the
+// lane's open count now.
+__device__ __forceinline__ void settle_group(ProbeTrack &T, uint32_t c, uint32_t tl, uint32_t th,
+                                             uint32_t pc)
+{
+    if (T.pk != 0 && __ballot(c != pc) != 0) {
+        T.lastk = T.pk;
+        T.gl = tl;
+        T.gh = th;
+    }
+    T.pk = 0;
 }
 
 __host__ __device__ constexpr uint32_t word_pattern(uint32_t p)
@@ -310,14 +336,17 @@ __device__ __forceinline__ bool small_prime_35(int64_t q)
 
 // Settle a lane's block after its grouped entries (called by whole waves):
 // the entries after the last full group one at a time, the gap-form checksum
-// correction for evens still open, the replay of the last group with a hit
-// (its last hitting entry is the block's largest p_min, the lowest bit of that
-// hit the smallest n attaining it; every entry replayed was tested before, so
-// the replay reproduces the same hits), and the spill of evens still open.
-// Bit i of the block is the even nbase + 6i.
+// correction for evens still open, the replay of the wave's last group with a
+// hit (all lanes of a wave read one table, so that group holds the wave's
+// largest p_min; a lane replays it from its open masks at the group's start,
+// and the lowest bit of its last hit is its smallest n with that p; every
+// entry replayed was tested before, so the replay reproduces the same hits),
+// and the spill of evens still open.  lastk (uniform) is the first entry of
+// that group, 0 if none; gl, gh the lane's masks at its start.  Bit i of the
+// block is the even nbase + 6i.
 __device__ __forceinline__ void finish_block(const GbProbeArgs &a, const char *lds, uint32_t base4,
                                              uint32_t tab, uint32_t nv, uint32_t k, uint32_t ul,
-                                             uint32_t uh, uint32_t acc, uint32_t lastg,
+                                             uint32_t uh, uint32_t acc, uint32_t lastk,
                                              uint32_t gl, uint32_t gh, uint32_t open0,
                                              uint64_t nbase, uint32_t ivx, uint64_t &sum,
                                              uint32_t &nres, uint32_t &bestp, uint64_t &bestn)
@@ -327,11 +356,13 @@ __device__ __forceinline__ void finish_block(const GbProbeArgs &a, const char *l
     if (__ballot((ul | uh) != 0) != 0) {
         for (; k <= nv; ++k) {
             const uint32_t sl = ul, sh = uh;
-            probe_one(lds, base4, ct[k - 1].off, ct[k - 1].sh, ct[k - 1].gap, ul, uh, acc);
-            const bool any = (ul != sl) | (uh != sh);
-            lastg = any ? k : lastg;
-            gl = any ? sl : gl;
-            gh = any ? sh : gh;
+            probe_one(lds, base4, ct[k - 1].off, ct[k - 1].sh, ct[k - 1].gap, open_count(ul, uh),
+                      ul, uh, acc);
+            if (__ballot((ul != sl) | (uh != sh)) != 0) {
+                lastk = k;
+                gl = sl;
+                gh = sh;
+            }
             if (__ballot((ul | uh) != 0) == 0) {
                 ++k;
                 break;
@@ -347,12 +378,12 @@ __device__ __forceinline__ void finish_block(const GbProbeArgs &a, const char *l
     // magnitude < 2^31 and is added sign-extended
     sum += (uint64_t)(int64_t)(int32_t)acc;
     nres += open0 - open;
-    if (lastg) {
+    if (lastk) {
         uint32_t vl = gl, vh = gh, lastp = 0, hl = 0, hh = 0;
-        const uint32_t kend = lastg + 3 < nv ? lastg + 3 : nv;
+        const uint32_t kend = lastk + 3 < nv ? lastk + 3 : nv;
         const uint32_t *tabv = a.ctab + (uint64_t)tab * 3 * kCandStride;
         const uint32_t *ptv = a.ptab + (uint64_t)tab * kCandStride;
-        for (uint32_t kk = lastg; kk <= kend && (vl | vh); ++kk) {
+        for (uint32_t kk = lastk; kk <= kend && (vl | vh); ++kk) {
             const uint32_t *e = tabv + 3 * (kk - 1);
             const uint32_t addr = base4 - e[0];
             const uint32_t w0 = *(const uint32_t *)(lds + addr);
@@ -735,33 +766,56 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
             const uint32_t ngrp = nv >> 2;
             const uint32_t base4 = ((act ? 2 * m : 0) + H96) * 4;  // byte address of the lane's first word
             uint32_t acc = 0;     // gap-form checksum, < 64 * 2^16 per block
-            uint32_t lastg = 0;   // first entry of the last group with a hit
-            uint32_t gl = 0;      // open evens at the start of that group
-            uint32_t gh = 0;
+            ProbeTrack T = {0, 0, 0, 0};
+            uint32_t tl0 = 0, th0 = 0, pc0 = 0, tl1 = 0, th1 = 0, pc1 = 0;
             uint32_t qopen = 0;   // evens handed to the second pass
             uint32_t k = 1;       // next entry (1-based)
-            for (uint32_t g = 0; g < ngrp; ++g) {
-                if (g == ka) {
-                    if (ul | uh) {
-                        const uint32_t slot = atomicAdd(&qn[r], 1u);
-                        if (slot < kQueue) {
-                            qm[r][slot] = (uint16_t)m;
-                            ql[r][slot] = ul;
-                            qh[r][slot] = uh;
-                            qopen = (uint32_t)(__popc(ul) + __popc(uh));
-                            ul = 0;
-                            uh = 0;
-                        }
-                    }
-                    if (__ballot((ul | uh) != 0) == 0)
-                        break;
-                }
-                probe_group(lds, base4, gt + g, k, ul, uh, acc, lastg, gl, gh);
-                k += 4;
-                if (__ballot((ul | uh) != 0) == 0)
-                    break;
+            // One group: settle the previous one (start state in set P), hand
+            // the lane's block to the second pass at group ka, stop when no
+            // lane is open, else keep this group's start state in set S and
+            // run it.
+#define GB_FIRST_PASS_GROUP(TLS, THS, PCS, TLP, THP, PCP)                      \
+            {                                                                  \
+                uint32_t c = open_count(ul, uh);                               \
+                settle_group(T, c, TLP, THP, PCP);                             \
+                if (g == ka) {                                                 \
+                    if (c != 0) {                                              \
+                        const uint32_t slot = atomicAdd(&qn[r], 1u);           \
+                        if (slot < kQueue) {                                   \
+                            qm[r][slot] = (uint16_t)m;                         \
+                            ql[r][slot] = ul;                                  \
+                            qh[r][slot] = uh;                                  \
+                            qopen = c;                                         \
+                            ul = 0;                                            \
+                            uh = 0;                                            \
+                            c = 0;                                             \
+                        }                                                      \
+                    }                                                          \
+                }                                                              \
+                if (__ballot(c != 0) == 0)                                     \
+                    break;                                                     \
+                TLS = ul;                                                      \
+                THS = uh;                                                      \
+                PCS = c;                                                       \
+                T.pk = k;                                                      \
+                probe_group(lds, base4, gt + g, c, ul, uh, acc);               \
+                k += 4;                                                        \
+                if (++g >= ngrp)                                               \
+                    break;                                                     \
             }
-            finish_block(a, lds, base4, tab, nv, k, ul, uh, acc, lastg, gl, gh, open0 - qopen,
+            uint32_t g = 0;
+            bool odd = false;   // the group just run keeps its state in set 1
+            if (ngrp > 0) {
+                for (;;) {
+                    odd = false;
+                    GB_FIRST_PASS_GROUP(tl0, th0, pc0, tl1, th1, pc1)
+                    odd = true;
+                    GB_FIRST_PASS_GROUP(tl1, th1, pc1, tl0, th0, pc0)
+                }
+            }
+#undef GB_FIRST_PASS_GROUP
+            settle_group(T, open_count(ul, uh), odd ? tl1 : tl0, odd ? th1 : th0, odd ? pc1 : pc0);
+            finish_block(a, lds, base4, tab, nv, k, ul, uh, acc, T.lastk, T.gl, T.gh, open0 - qopen,
                          n0 + 2ull * r + 384ull * m, ivx, sum, nres, bestp, bestn);
         }
         // The next segment is claimed here by the last wave, which takes no
@@ -795,15 +849,39 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                 const uint32_t nv = a.nv[r * 3 + t3];
                 const uint32_t ngrp = nv >> 2;
                 const uint32_t base4 = (2 * m + H96) * 4;
-                uint32_t acc = 0, lastg = 0, gl = 0, gh = 0;
+                uint32_t acc = 0;
+                ProbeTrack T = {0, 0, 0, 0};
+                uint32_t tl0 = 0, th0 = 0, pc0 = 0, tl1 = 0, th1 = 0, pc1 = 0;
                 uint32_t k = 4 * ka + 1;
-                for (uint32_t g = ka; g < ngrp; ++g) {
-                    probe_group(lds, base4, gt + g, k, ul, uh, acc, lastg, gl, gh);
-                    k += 4;
-                    if (__ballot((ul | uh) != 0) == 0)
-                        break;
+#define GB_SECOND_PASS_GROUP(TLS, THS, PCS, TLP, THP, PCP)                     \
+                {                                                              \
+                    const uint32_t c = open_count(ul, uh);                     \
+                    settle_group(T, c, TLP, THP, PCP);                         \
+                    if (__ballot(c != 0) == 0)                                 \
+                        break;                                                 \
+                    TLS = ul;                                                  \
+                    THS = uh;                                                  \
+                    PCS = c;                                                   \
+                    T.pk = k;                                                  \
+                    probe_group(lds, base4, gt + g, c, ul, uh, acc);           \
+                    k += 4;                                                    \
+                    if (++g >= ngrp)                                           \
+                        break;                                                 \
                 }
-                finish_block(a, lds, base4, tab, nv, k, ul, uh, acc, lastg, gl, gh, open0,
+                uint32_t g = ka;
+                bool odd = false;
+                if (g < ngrp) {
+                    for (;;) {
+                        odd = false;
+                        GB_SECOND_PASS_GROUP(tl0, th0, pc0, tl1, th1, pc1)
+                        odd = true;
+                        GB_SECOND_PASS_GROUP(tl1, th1, pc1, tl0, th0, pc0)
+                    }
+                }
+#undef GB_SECOND_PASS_GROUP
+                settle_group(T, open_count(ul, uh), odd ? tl1 : tl0, odd ? th1 : th0,
+                             odd ? pc1 : pc0);
+                finish_block(a, lds, base4, tab, nv, k, ul, uh, acc, T.lastk, T.gl, T.gh, open0,
                              n0 + 2ull * r + 384ull * m, ivx, sum, nres, bestp, bestn);
             }
         }
