@@ -88,7 +88,7 @@ __device__ void fill_tile(const GbBucketArgs &a, uint64_t tile)
                     d = dsq;
             }
             // the odd number Q0 + 2d is a multiple of 3 when d = Q0 (mod 3):
-            // the window keeps those bits clear, so they are not struck
+            // the window does not store that class, so those bits are not struck
             const uint32_t q0m3 = (uint32_t)(Q0 % 3);
             uint32_t dm3 = (uint32_t)(d % 3);
             for (; d <= dmax; d += p) {

@@ -28,7 +28,7 @@
 //   * primes >= 37   strikes from max(p^2, first multiple in the window) with
 //                    LDS atomic OR, class by class (a prime's
 //                    multiples in one class are p class bits apart); primes up
-//                    to E/512 are cleared by one wave each (each lane keeps one
+//                    to E/512 are struck by one wave each (each lane keeps one
 //                    bit position, so its mask is loop-invariant), larger ones
 //                    one prime per thread with several table loads in flight;
 //   * primes above the bucket bound (when the launch has buckets) are not
@@ -496,7 +496,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
     const uint32_t WCU = a.wcu;    // class-array words in use
     const uint32_t *__restrict__ primes = a.primes;
     const cprime_t cp = (cprime_t)primes;
-    // primes[kFirstStrided .. nwave) are cleared one prime per wave
+    // primes[kFirstStrided .. nwave) are struck one prime per wave
     const uint32_t nwave = count_le(primes, a.nprimes, kWaveTierMax);
     const uint32_t tabbase = (uint32_t)(LOG2E - 18) * 9;
 
@@ -607,7 +607,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                 }
             }
         }
-        // restore the primes 3..31 and clear q <= 1 where the window reaches them
+        // unmark the primes 3..31 and mark q <= 1 where the window reaches them
         if (neg || qlo <= 35) {
             __syncthreads();
             const uint64_t bmax = neg ? (35 + qneg) >> 1 : (35 - qlo) >> 1;  // odd bits 0..bmax
@@ -630,7 +630,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
         __syncthreads();
 
         const uint32_t nroot = __builtin_amdgcn_readfirstlane(sh_nroot);  // published by the barrier above
-        const uint32_t nsieve = nroot < a.lb_count ? nroot : a.lb_count;  // primes cleared here
+        const uint32_t nsieve = nroot < a.lb_count ? nroot : a.lb_count;  // primes struck here
 
         // ---- strikes, one prime per wave: 37 <= p <= kWaveTierMax ----
         // The prime's odd multiples b = j0 + kp fall in the two stored
@@ -905,7 +905,11 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
             red_n[wave] = bestn;
         }
         __syncthreads();
-        GbSegRecord rec;
+        // Thread 0 combines the waves' partials after the barrier that ends
+        // this pass of the loop: the other waves start the next segment
+        // meanwhile, and none writes red_* again before the presieve barrier
+        // of that segment, which thread 0 reaches only after this.  The
+        // interval is complete when its last segment record is written.
         if (tid == 0) {
             uint64_t s = 0, c = 0, bn = 0;
             uint32_t bp = 0;
@@ -917,17 +921,12 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                     bn = red_n[w];
                 }
             }
+            GbSegRecord rec;
             rec.checksum = s;
             rec.verified = c;
             rec.max_p = bp;
             rec.max_n = bp ? bn : 0;
             rec.pad = 0;
-        }
-        __syncthreads();
-        // the record is written after the barrier, so the other waves start
-        // the next segment while this one waits on the fence; the interval
-        // is complete when its last segment record is written
-        if (tid == 0) {
             a.rec[seg] = rec;
             __threadfence();
             if (atomicAdd(&a.done[ivx].segs_done, 1ull) + 1 == iv_nseg)
