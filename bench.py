@@ -80,24 +80,29 @@ KERNEL_SOURCES = ("paper_2603_07850_amd/csrc/gb_sieve.hip", "paper_2603_07850_am
                   "paper_2603_07850_amd/csrc/gb_internal.h")
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed counter summary, or None when the
-    kernel sources changed since the counters were taken."""
+def profile_figures():
+    """Counter figures of the sieve+probe kernel from the committed summary:
+    HBM bytes per launch and the VALU issue fraction (instructions issued over
+    the one-per-CU-per-cycle peak), or None for each when the kernel sources
+    changed since the counters were taken."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "sieve_probe_1e12.md")
     if not os.path.exists(path):
-        return None
+        return None, None
     text = open(path).read()
     m = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    v = re.search(r"valu_issue_frac: ([0-9.]+)", text)
     h = re.search(r"kernel_source_sha256_16: ([0-9a-f]+)", text)
-    if not m or not h:
-        return None
+    if not h:
+        return None, None
     sha = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             sha.update(fh.read())
-    return int(m.group(1)) if sha.hexdigest()[:16] == h.group(1) else None
+    if sha.hexdigest()[:16] != h.group(1):
+        return None, None
+    return (int(m.group(1)) if m else None), (float(v.group(1)) if v else None)
 
 
 def cpu_baseline(sample_windows):
@@ -300,10 +305,14 @@ def main():
     ops_even = algorithmic_ops_per_even(wm, st["seg_log2"], st["halo_bits"])
     kern_s = sum(probe_ms) / len(probe_ms) / 1e3
     achieved = ops_even * evens / kern_s
+    traffic, valu_issue = profile_figures()
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": measured_traffic(),
+                "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": traffic,
                 "kernel": "sieve_probe_kernel", "kernel_ms": kern_s * 1e3,
-                "ops_per_even": ops_even}
+                "ops_per_even": ops_even,
+                # the issue roofline from the counters: VALU instructions issued
+                # over the peak of one wave64 instruction per CU per cycle
+                "valu_issue_frac": valu_issue}
 
     out = {
         "metric": "even n verified/sec at 1 GPU (to 1e12)",
