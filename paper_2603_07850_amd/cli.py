@@ -236,9 +236,19 @@ def parse_args(argv):
 
 
 def main(argv=None):
+    """Exit status: 0 verified, 1 some even left unresolved by every test (a
+    counterexample candidate), 2 an error (library, resources or log), 3 a run
+    stopped before the end of the range."""
     a = parse_args(sys.argv[1:] if argv is None else argv)
     from . import _binding as gb   # loads the HIP library; raises if it is not built
+    try:
+        return _main(a, gb)
+    except (gb.GoldbachError, ValueError, OSError) as e:
+        print("goldbach: %s" % e, file=sys.stderr, flush=True)
+        return 2
 
+
+def _main(a, gb):
     nb = normalize(a.start, a.limit)
     base = a.base_limit or max(math.isqrt(nb[1]) if nb else 0, a.p_max)
     gb.base_primes(base)

@@ -61,3 +61,13 @@ def test_cli_start_partitions_the_range(whole):
     m = merge(merge(empty_result(), dict(lo, unresolved=[]), 16), dict(hi, unresolved=[]), 16)
     for f in CMP:
         assert m[f] == whole[f], f
+
+
+@pytest.mark.gpu
+def test_cli_reports_errors():
+    # a prime table below isqrt(LIMIT) is refused before any work (exit status 2)
+    cmd = [sys.executable, "-m", "paper_2603_07850_amd", str(10 ** 12), "--base-limit", "1000",
+           "--seg-log2", "18", "--wg-size", "256"]
+    print("[gpu] %s" % " ".join(cmd[2:]), flush=True)
+    p = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=240)
+    assert p.returncode == 2 and "GB_ERANGE" in p.stderr, (p.returncode, p.stderr[-2000:])
