@@ -98,8 +98,10 @@ typedef struct gb_result {
  *              run of segments; 17..32 (32 = never) applies to every range
  *              whose isqrt(B) exceeds the bound; 0 = automatic: bound
  *              2^(seg_log2 + 4).
- *   bucket_mib HBM budget for the strike bitmaps of one round, in MiB
- *              (0 = 512); larger batches run in several rounds.
+ *   bucket_mib HBM budget for the strike bitmaps of one round, in MiB;
+ *              0 = automatic: 512 for the first round, 8192 for the next
+ *              ones.  Larger batches run in several rounds.  Only the
+ *              bitmaps of the segments a round holds are allocated.
  */
 typedef struct gb_params {
     uint32_t seg_log2;

@@ -413,6 +413,17 @@ struct Plan {
 // pi(x) < 1.25506 x / ln x for x > 1 (Rosser and Schoenfeld 1962).
 uint64_t pi_upper(uint64_t x) { return (uint64_t)(1.25506 * (double)x / std::log((double)x)) + 16; }
 
+// Automatic strike-bitmap budget (bucket_mib = 0): a first round of
+// kBucketMibFirst MiB, then rounds of kBucketMibDefault MiB.  Each round is one
+// fill launch and one persistent sieve launch, each of which drains at its
+// end, so few large rounds beat many small ones (a 4096-interval batch near
+// 2^64: 0.218 s per launch in 512 MiB rounds, 0.188 s in one 4-16 GiB round);
+// the small first round finishes the cheapest intervals of the batch early
+// (median completion 24 ms instead of 141 ms, at 0.192 s per launch).  Memory
+// is taken only for the segments a round holds.
+constexpr uint32_t kBucketMibFirst = 512;
+constexpr uint32_t kBucketMibDefault = 8192;
+
 gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, const gb_params &pr,
                     Plan &pl)
 {
@@ -451,7 +462,13 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
         blog = 32;
     pl.lb = blog >= 32 ? 0xFFFFFFFFull : (1ull << blog);
     pl.lb_count = (uint32_t)std::min<uint64_t>(blog >= 32 ? c.nprimes : c.pi2[blog], c.nprimes);
-    const uint64_t budget = (uint64_t)(pr.bucket_mib ? pr.bucket_mib : 512) << 20;
+    const bool auto_budget = pr.bucket_mib == 0;
+    const uint64_t budget = (uint64_t)(auto_budget ? kBucketMibDefault : pr.bucket_mib) << 20;
+    // budget of the round being filled (the first one smaller when
+    // automatic); a chunk is cut to fit the smallest round
+    uint64_t round_budget = auto_budget ? std::min<uint64_t>(budget, (uint64_t)kBucketMibFirst << 20)
+                                        : budget;
+    const uint64_t chunk_budget = round_budget;
     pl.wcu = (uint32_t)((Wbits + 95) / 96 + 1);
     pl.words = 3 * pl.wcu;
 
@@ -568,10 +585,10 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
         const uint64_t i = order[oi];
         const GbInterval &I = pl.iv[i];
         // chunk length: a chunk's strike bitmaps fit one round within the budget
-        uint64_t cmax = budget / ((uint64_t)pl.words * 4);
+        uint64_t cmax = chunk_budget / ((uint64_t)pl.words * 4);
         if (cmax < 1) {
             set_err("bucket budget of %llu MiB is below one segment's strike bitmap",
-                    (unsigned long long)(budget >> 20));
+                    (unsigned long long)(chunk_budget >> 20));
             return GB_ENOMEM;
         }
         cmax = std::min<uint64_t>(cmax, 1u << 16);
@@ -587,8 +604,11 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
             ch.Q0 = n0 - 1 - 2ull * pl.H;                         // n0 > 2H + 2 here
             ch.dmax = (top - ch.Q0) / 2;
             ch.p_root = 0;                                        // set on the device
-            if (cur.nsegs && (cur.nsegs + ns) * (uint64_t)pl.words * 4 > budget)
+            if (cur.nsegs && (cur.nsegs + ns) * (uint64_t)pl.words * 4 > round_budget) {
                 close_round();
+                if (auto_budget)
+                    round_budget = budget;
+            }
             cur.bm = 1;
             ch.seg_first = I.seg_first + s0;
             cur.nsegs += ns;
