@@ -18,7 +18,8 @@ Extra legs (also in the JSON line):
   batched       4096 seeded uneven intervals in one persistent launch vs one
                 launch per interval, with p50/p99 latency (off: --no-batched);
   served        the seeded Poisson request trace through the continuous-
-                batching server at 0.7x the batched capacity (off: --no-served).
+                batching server at 0.7x the batched capacity, against the same
+                arrivals served one gb_verify_range at a time (off: --no-served).
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
                        [--no-batched] [--no-served]
@@ -204,11 +205,28 @@ def run_served(gb, capacity_evens_per_s, load=0.7, n_requests=2000, seed=3001):
         wall = time.perf_counter() - t0
         st = srv.stats()
     q = lambda xs, p: sorted(xs)[min(len(xs) - 1, int(p * len(xs)))]
-    return {"requests": len(trace), "offered_load": load, "arrival_rate_per_s": rate,
-            "evens": total_evens, "evens_per_s": total_evens / wall, "wall_s": wall,
-            "p50_ms": q(lat, 0.5) * 1e3, "p99_ms": q(lat, 0.99) * 1e3,
-            "ticks": st["ticks"], "busy_frac": st["busy_ms"] / (wall * 1e3),
-            "all_verified": all(done)}
+    out = {"requests": len(trace), "offered_load": load, "arrival_rate_per_s": rate,
+           "evens": total_evens, "evens_per_s": total_evens / wall, "wall_s": wall,
+           "p50_ms": q(lat, 0.5) * 1e3, "p99_ms": q(lat, 0.99) * 1e3,
+           "ticks": st["ticks"], "busy_frac": st["busy_ms"] / (wall * 1e3),
+           "all_verified": all(done)}
+    # plain per-request baseline: the same arrivals, one gb_verify_range per
+    # request in arrival order (a FIFO queue in front of one launch at a time)
+    lat1 = []
+    t0 = time.perf_counter()
+    for i, (t, a, b) in enumerate(trace):
+        dt = t - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        gb.verify_range(a, b, 65536)
+        lat1.append(time.perf_counter() - t0 - t)
+        if i % 500 == 499:
+            log("per-request baseline: %d / %d requests done" % (i + 1, len(trace)))
+    wall1 = time.perf_counter() - t0
+    out.update({"per_request_evens_per_s": total_evens / wall1, "per_request_wall_s": wall1,
+                "per_request_p50_ms": q(lat1, 0.5) * 1e3,
+                "per_request_p99_ms": q(lat1, 0.99) * 1e3})
+    return out
 
 
 def copy_calibration():
