@@ -160,6 +160,18 @@ gb_status gb_verify_range(uint64_t A, uint64_t B, uint64_t P_max, void *stream,
 gb_status gb_verify_batch(const uint64_t *AB, uint64_t k, uint64_t P_max,
                           void *stream, gb_result *outs);
 
+/*
+ * Test hook for the failure paths (Sec. 3.4, graceful error handling: an
+ * error is reported, the library stays usable).  Makes the next
+ * gb_verify_range / gb_verify_batch call fail with GB_EHIP at point `where`:
+ * 1 = after validation, before anything is enqueued; 2 = after its kernels
+ * are enqueued, before the results are read.  A failed call returns only when
+ * none of its work is still in flight, and the next call runs normally.
+ * where = 0 clears a pending injection; other values give GB_EINVAL.  No
+ * kernel is made to fail: the condition is forced on the host.
+ */
+gb_status gb_debug_fail_next(uint32_t where);
+
 /* Set / read the launch parameters used by later verify calls.  GB_EINVAL on
  * values outside the documented sets. */
 gb_status gb_set_params(const gb_params *p);

@@ -91,6 +91,7 @@ def lib():
         "gb_autotune_batch": (st, [ctypes.POINTER(ctypes.c_uint64), u64, u64, vp, ctypes.POINTER(Params)]),
         "gb_is_prime_u64": (st, [vp, u64, vp, vp]),
         "gb_last_stats": (st, [ctypes.POINTER(Stats)]),
+        "gb_debug_fail_next": (st, [ctypes.c_uint32]),
         "gb_last_latencies": (st, [vp, u64]),
         "gb_server_open": (st, [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
         "gb_server_submit": (st, [vp, u64, u64, ctypes.POINTER(u64)]),
@@ -232,6 +233,12 @@ def is_prime_u64(q):
     _check(lib().gb_is_prime_u64(q.data_ptr(), q.numel(), out.data_ptr(),
                                  torch.cuda.current_stream(q.device).cuda_stream))
     return out
+
+
+def debug_fail_next(where):
+    """Test hook: the next verify call fails with GB_EHIP at point `where`
+    (1 before enqueue, 2 after the kernels are enqueued; 0 clears)."""
+    _check(lib().gb_debug_fail_next(int(where)))
 
 
 def last_stats():

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -771,11 +772,20 @@ gb_status capture_graph(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params 
     return GB_OK;
 }
 
+// Failure injected by gb_debug_fail_next() into the next run: 1 before
+// anything is enqueued, 2 after the kernels are enqueued.
+std::atomic<uint32_t> g_fail_next{0};
+
 // One pass of the launch sequence; the caller retries when a capacity
-// (spill list, bucket) overflowed.
-gb_status run_once(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr, hipStream_t s,
-                   bool use_graph, uint64_t *spills_out)
+// (spill list, bucket) overflowed.  `enqueued` is set once work is on s.
+gb_status run_once_impl(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr,
+                        hipStream_t s, bool use_graph, uint64_t *spills_out, bool &enqueued)
 {
+    const uint32_t inject = g_fail_next.exchange(0, std::memory_order_relaxed);
+    if (inject == 1) {
+        set_err("failure injected before anything was enqueued (test hook)");
+        return GB_EHIP;
+    }
     const uint64_t k = pl.iv.size();
     const uint64_t nr = std::max<size_t>(pl.rounds.size(), 1);
     GB_TRY(c.d_iv.reserve(k * sizeof(GbInterval)));
@@ -810,6 +820,7 @@ gb_status run_once(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr, 
         grid = (uint32_t)std::min<uint64_t>(pl.total_segs, (uint64_t)c.num_cu * occ);
     }
     std::memcpy(c.h_iv.p, pl.dev_iv.data(), k * sizeof(GbInterval));
+    enqueued = true;
     GB_HIP(hipMemcpyAsync(c.d_iv.p, c.h_iv.p, k * sizeof(GbInterval), hipMemcpyHostToDevice, s));
     if (!pl.chunks.empty()) {
         std::memcpy(c.h_chunk.p, pl.chunks.data(), pl.chunks.size() * sizeof(GbChunk));
@@ -828,6 +839,10 @@ gb_status run_once(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr, 
         GB_HIP(hipGraphLaunch(c.graph_exec, s));
     } else {
         GB_TRY(enqueue_kernels(c, pl, P_max, pr, grid, s, true));
+    }
+    if (inject == 2) {
+        set_err("failure injected after the kernels were enqueued (test hook)");
+        return GB_EHIP;
     }
     GB_HIP(hipMemcpyAsync(c.h_res.p, c.d_res.p, k * sizeof(GbIvResult), hipMemcpyDeviceToHost, s));
     GB_HIP(hipMemcpyAsync(c.h_ctr.p, c.d_ctr.p, sizeof(GbCounters), hipMemcpyDeviceToHost, s));
@@ -863,6 +878,20 @@ gb_status run_once(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr, 
     st.ncand = pl.ncand;
     st.intervals = k;
     return GB_OK;
+}
+
+gb_status run_once(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr, hipStream_t s,
+                   bool use_graph, uint64_t *spills_out)
+{
+    bool enqueued = false;
+    const gb_status st = run_once_impl(c, pl, P_max, pr, s, use_graph, spills_out, enqueued);
+    if (st != GB_OK && enqueued) {
+        // a failed call returns only when none of its work is still in flight,
+        // so the next call may reuse every buffer, pinned staging included
+        (void)hipStreamSynchronize(s);
+        (void)hipGetLastError();
+    }
+    return st;
 }
 
 gb_status verify_many(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, hipStream_t s,
@@ -1142,6 +1171,17 @@ gb_status gb_release(void)
     if (c.device >= 0)
         (void)hipSetDevice(c.device);
     release_all(c);
+    return GB_OK;
+}
+
+gb_status gb_debug_fail_next(uint32_t where)
+{
+    if (where > 2) {
+        set_err("gb_debug_fail_next: where must be 0, 1 or 2 (got %u)", where);
+        return GB_EINVAL;
+    }
+    g_fail_next.store(where, std::memory_order_relaxed);
+    g_err.clear();
     return GB_OK;
 }
 

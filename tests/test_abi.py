@@ -97,3 +97,11 @@ def test_build_flags_keep_miscompiled_forms_out():
     flags = " ".join(build.FLAGS)
     assert "-target-feature -Xclang -packed-fp32-ops" in flags
     assert "-target-feature -Xclang -bitop3-insts" in flags
+
+
+def test_failure_hook_validates_its_argument(gb):
+    with pytest.raises(gb.GoldbachError) as e:
+        gb.debug_fail_next(3)
+    assert e.value.name == "GB_EINVAL"
+    gb.debug_fail_next(1)
+    gb.debug_fail_next(0)           # cleared again: nothing pending for later tests

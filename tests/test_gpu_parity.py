@@ -330,3 +330,37 @@ def test_range_autotuner_keeps_results(gb, O):
         check(gb, O, 10**11, 10**11 + 2 * 4_000_000, 65536, 10**6)
     finally:
         gb.set_params(**saved)
+
+
+def same(g, o):
+    for f in FIELDS:
+        assert g[f] == o[f], (f, g[f], o[f])
+
+
+@pytest.mark.gpu
+def test_injected_failures_leave_the_library_usable(gb, O):
+    """A call that fails before or after its kernels are enqueued (forced on
+    the host through the test hook) reports GB_EHIP, and the next calls give
+    the oracle's results (paper Sec. 3.4: errors are reported, not fatal)."""
+    table(gb, 10 ** 6)
+    gb.set_params(seg_log2=19, wg_size=1024, window=4096)
+    A, B, P_max = 10 ** 9, 10 ** 9 + 4 * 10 ** 6, 65536
+    want = O.verify_range(A, B, P_max, 10 ** 6)
+    ivs = [(10 ** 9, 10 ** 9 + 10 ** 6), (4, 10 ** 6), (10 ** 10, 10 ** 10 + 2 * 10 ** 6)]
+    want_b = [O.verify_range(a, b, P_max, 10 ** 6) for a, b in ivs]
+    for where in (1, 2, 1, 2):
+        print("[gpu] injected failure at point %d" % where, flush=True)
+        gb.debug_fail_next(where)
+        with pytest.raises(gb.GoldbachError) as e:
+            gb.verify_range(A, B, P_max)
+        assert e.value.name == "GB_EHIP" and "injected" in str(e.value)
+        same(gb.verify_range(A, B, P_max), want)
+        gb.debug_fail_next(where)
+        with pytest.raises(gb.GoldbachError) as e:
+            gb.verify_batch(ivs, P_max)
+        assert e.value.name == "GB_EHIP"
+        for g, o in zip(gb.verify_batch(ivs, P_max), want_b):
+            same(g, o)
+    gb.debug_fail_next(2)
+    gb.debug_fail_next(0)
+    same(gb.verify_range(A, B, P_max), want)
