@@ -313,6 +313,10 @@ def main():
         probe_ms.append(gb.last_stats()["probe_ms"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    import statistics
+    timing = {"kernel_ms_each": probe_ms, "kernel_ms_median": statistics.median(probe_ms),
+              "kernel_cov": (statistics.pstdev(probe_ms) / statistics.fmean(probe_ms)
+                             if len(probe_ms) > 1 else 0.0)}
     st = gb.last_stats()
     ok = (r["verified"] == evens and r["n_unresolved"] == 0 and r["n_failed"] == 0)
     if args.warmup:
@@ -345,6 +349,7 @@ def main():
                                      "n_unresolved", "n_failed")},
         "results_consistent": ok,
         "roofline": roofline,
+        "timing": timing,
     }
     if not args.no_batched:
         # batches reach 2^64: their launch parameters come from the batch
