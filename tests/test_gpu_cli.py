@@ -13,13 +13,21 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CMP = ("verified", "checksum", "max_p", "max_p_n", "n_unresolved", "n_failed")
 
 
-def cli(*args, timeout=240):
+def cli(*args, timeout=600):
     cmd = [sys.executable, "-m", "paper_2603_07850_amd"] + [str(a) for a in args]
     print("[gpu] %s" % " ".join(cmd[2:]), flush=True)
     p = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=timeout)
     lines = [l for l in p.stdout.splitlines() if l.startswith("{")]
     assert lines, (p.returncode, p.stdout[-2000:], p.stderr[-2000:])
     return p.returncode, json.loads(lines[-1]), p.stderr
+
+
+@pytest.fixture(scope="module", autouse=True)
+def warm_torch():
+    # the first import of torch on a fresh machine pages in its libraries
+    # (a minute or more); do it here once, not inside a child's time limit
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
 
 
 @pytest.fixture(scope="module")
@@ -69,5 +77,5 @@ def test_cli_reports_errors():
     cmd = [sys.executable, "-m", "paper_2603_07850_amd", str(10 ** 12), "--base-limit", "1000",
            "--seg-log2", "18", "--wg-size", "256"]
     print("[gpu] %s" % " ".join(cmd[2:]), flush=True)
-    p = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=240)
+    p = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert p.returncode == 2 and "GB_ERANGE" in p.stderr, (p.returncode, p.stderr[-2000:])
