@@ -399,10 +399,16 @@ __device__ __forceinline__ void finish_block(const GbProbeArgs &a, const char *l
                 hh = xh;
             }
         }
-        if (lastp > bestp) {
-            bestp = lastp;
+        // A lane runs several blocks, not in ascending n (class by class, then
+        // the second-pass queue), so an equal p keeps the smaller n, as every
+        // later merge of the aggregates does.
+        if (lastp != 0) {
             const uint32_t bit = hl ? (uint32_t)(__ffs(hl) - 1) : 32u + (uint32_t)(__ffs(hh) - 1);
-            bestn = nbase + 6ull * bit;
+            const uint64_t n = nbase + 6ull * bit;
+            if (lastp > bestp || (lastp == bestp && n < bestn)) {
+                bestp = lastp;
+                bestn = n;
+            }
         }
     }
     while (ul | uh) {

@@ -364,3 +364,31 @@ def test_injected_failures_leave_the_library_usable(gb, O):
     gb.debug_fail_next(2)
     gb.debug_fail_next(0)
     same(gb.verify_range(A, B, P_max), want)
+
+
+def _max_ties():
+    import json
+    with open(os.path.join(os.path.dirname(__file__), "golden", "max_ties.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("shape", LAUNCH_SHAPES, ids=lambda s: "w%d_t%d_win%d" % s)
+def test_max_ties_smallest_n(gb, shape):
+    """Windows whose largest p_min is attained by two or more n (oracle fixture):
+    max_p_n is the smallest of them at every launch shape, alone and in a batch.
+    A lane visits several blocks, not in ascending n, so a tie kept in visiting
+    order instead of by n shows up here."""
+    d = _max_ties()
+    table(gb, d["limit"])
+    lg, wg, win = shape
+    saved = gb.get_params()
+    try:
+        gb.set_params(seg_log2=lg, wg_size=wg, window=win)
+        wins = d["windows"]
+        got_b = gb.verify_batch([(w["A"], w["B"]) for w in wins], d["P_max"])
+        for w, gbat in zip(wins, got_b):
+            g = gb.verify_range(w["A"], w["B"], d["P_max"])
+            for f in ("verified", "checksum", "max_p", "max_p_n"):
+                assert g[f] == gbat[f] == w[f], (f, w["A"], g[f], gbat[f], w[f])
+    finally:
+        gb.set_params(**saved)
