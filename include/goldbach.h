@@ -304,6 +304,27 @@ gb_status gb_server_get_stats(gb_server *s, gb_server_stats *out);
 /* Finish the active requests, drop the queued ones, stop the thread, free s. */
 gb_status gb_server_close(gb_server *s);
 
+/*
+ * Device memory allocator of the library (the resident tables and the
+ * workspaces of the verify calls and the server).  Paper Sec. 3.1 keeps the
+ * base primes and the work structures resident on the device; this hook lets
+ * the host framework own that memory, e.g. PyTorch's caching allocator.
+ *   alloc(bytes, stream, user)        returns device memory of at least
+ *                                     `bytes` bytes, or NULL (the call that
+ *                                     needed it then fails with GB_ENOMEM);
+ *   free_(ptr, bytes, stream, user)   gives back what alloc returned.
+ * The library passes stream = NULL: its buffers are used on any stream, and
+ * the device is synchronized before any of them is given back.  Both
+ * functions NULL restores hipMalloc / hipFree.  Setting an allocator first
+ * releases everything the library holds (as gb_release(), each buffer going
+ * back to the allocator that gave it), so it is called before
+ * gb_base_primes() and never while a server is open.  The functions may be
+ * called from the server's thread.  GB_EINVAL if exactly one is NULL.
+ */
+typedef void *(*gb_alloc_fn)(size_t bytes, void *stream, void *user);
+typedef void (*gb_free_fn)(void *ptr, size_t bytes, void *stream, void *user);
+gb_status gb_set_allocator(gb_alloc_fn alloc, gb_free_fn free_, void *user);
+
 /* Free the prime table and every workspace.  Safe to call at any time. */
 gb_status gb_release(void);
 

@@ -62,6 +62,11 @@ class ServerStats(ctypes.Structure):
                [("busy_ms", ctypes.c_double), ("wall_ms", ctypes.c_double)]
 
 
+# gb_alloc_fn / gb_free_fn of include/goldbach.h
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                           ctypes.c_void_p)
+
 RESULT_FIELDS = ("A", "B", "P_max", "verified", "max_p", "max_p_n", "checksum",
                  "n_unresolved", "n_failed")
 
@@ -85,6 +90,7 @@ def lib():
         "gb_table_read": (st, [vp, u64, u64]),
         "gb_verify_range": (st, [u64, u64, u64, vp, ctypes.POINTER(Result)]),
         "gb_verify_batch": (st, [vp, u64, u64, vp, vp]),
+        "gb_set_allocator": (st, [ALLOC_FN, FREE_FN, vp]),
         "gb_set_params": (st, [ctypes.POINTER(Params)]),
         "gb_get_params": (st, [ctypes.POINTER(Params)]),
         "gb_autotune": (st, [u64, u64, u64, vp, ctypes.POINTER(Params)]),
@@ -258,6 +264,107 @@ def last_batch_latencies():
 
 def release():
     _check(lib().gb_release())
+
+
+_allocator = {}   # the registered ctypes callbacks, kept alive while registered
+
+
+def set_allocator(alloc=None, free=None):
+    """gb_set_allocator with Python callables alloc(nbytes) -> int device
+    pointer (0 for failure) and free(ptr, nbytes); None, None restores
+    hipMalloc / hipFree.  Releases every table and buffer of the library."""
+    if alloc is None and free is None:
+        _check(lib().gb_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        _allocator.clear()
+        return
+
+    def _a(nbytes, stream, user):
+        try:
+            return int(alloc(int(nbytes))) or None
+        except Exception:       # reported to the library as "no memory"
+            return None
+
+    def _f(ptr, nbytes, stream, user):
+        try:
+            free(int(ptr), int(nbytes))
+        except Exception:
+            pass
+
+    cbs = (ALLOC_FN(_a), FREE_FN(_f))
+    _check(lib().gb_set_allocator(cbs[0], cbs[1], None))
+    _allocator["cbs"] = cbs
+
+
+def use_torch_allocator(device=None):
+    """Route every device allocation of the library through PyTorch's caching
+    allocator (memory only; no computation runs in torch).  Returns the
+    counters {'alloc': calls, 'free': calls, 'bytes': bytes held}."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+    count = {"alloc": 0, "free": 0, "bytes": 0}
+
+    def alloc(nbytes):
+        ptr = torch.cuda.caching_allocator_alloc(nbytes, dev)
+        count["alloc"] += 1
+        count["bytes"] += nbytes
+        return ptr
+
+    def free(ptr, nbytes):
+        torch.cuda.caching_allocator_delete(ptr)
+        count["free"] += 1
+        count["bytes"] -= nbytes
+
+    set_allocator(alloc, free)
+    return count
+
+
+class Server:
+    """Served form: continuous batching of submitted ranges (gb_server_*)."""
+
+    def __init__(self, P_max, hbm_budget_bytes=64 << 30, max_active=64, piece_segments=256,
+                 max_pending=0):
+        cfg = ServerConfig(int(hbm_budget_bytes), int(P_max), int(max_active),
+                           int(piece_segments), int(max_pending), 0)
+        self._h = ctypes.c_void_p()
+        _check(lib().gb_server_open(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self.P_max = int(P_max)
+
+    def submit(self, A, B):
+        rid = ctypes.c_uint64()
+        _check(lib().gb_server_submit(self._h, int(A), int(B), ctypes.byref(rid)))
+        return int(rid.value)
+
+    def poll(self, wait_ms=-1, unresolved_cap=1024):
+        """(id, result dict, latency seconds), or None if nothing finished in time."""
+        buf = (ctypes.c_uint64 * max(int(unresolved_cap), 1))()
+        r = Result()
+        r.unresolved = ctypes.cast(buf, ctypes.POINTER(ctypes.c_uint64))
+        r.unresolved_cap = int(unresolved_cap)
+        rid = ctypes.c_uint64()
+        lat = ctypes.c_double()
+        st = lib().gb_server_poll(self._h, int(wait_ms), ctypes.byref(rid), ctypes.byref(r),
+                                  ctypes.byref(lat))
+        if st == 7:
+            return None
+        _check(st, ok=(0, 5))
+        return int(rid.value), _to_dict(r, buf), lat.value / 1e3
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib().gb_server_get_stats(self._h, ctypes.byref(s)))
+        return {f: (float(getattr(s, f)) if f.endswith("_ms") else int(getattr(s, f)))
+                for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            _check(lib().gb_server_close(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Server:

@@ -54,13 +54,28 @@ void set_err(const char *fmt, ...)
             return s_;                 \
     } while (0)
 
+// Device memory of the library comes from the registered allocator
+// (gb_set_allocator; hipMalloc / hipFree by default).  A buffer remembers the
+// allocator that gave it its memory and returns the memory there.
+struct Allocator {
+    gb_alloc_fn alloc = nullptr;   // null: hipMalloc / hipFree
+    gb_free_fn free_ = nullptr;
+    void *user = nullptr;
+};
+Allocator g_alloc;   // guarded by the context lock
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    Allocator from;
     void release()
     {
-        if (p)
-            (void)hipFree(p);
+        if (p) {
+            if (from.alloc)
+                from.free_(p, bytes, nullptr, from.user);
+            else
+                (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
     }
@@ -71,13 +86,22 @@ struct DevBuf {
             return GB_OK;
         release();
         size_t want = std::max(need, (size_t)4096);
-        hipError_t e = hipMalloc(&p, want);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            set_err("hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
-            return GB_ENOMEM;
+        if (g_alloc.alloc) {
+            p = g_alloc.alloc(want, nullptr, g_alloc.user);
+            if (!p) {
+                set_err("registered allocator returned no memory for %zu bytes", want);
+                return GB_ENOMEM;
+            }
+        } else {
+            hipError_t e = hipMalloc(&p, want);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                p = nullptr;
+                set_err("hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+                return GB_ENOMEM;
+            }
         }
+        from = g_alloc;
         bytes = want;
         return GB_OK;
     }
@@ -205,6 +229,10 @@ bool params_valid(const gb_params &p)
 
 void release_all(Ctx &c)
 {
+    // memory may go back to a caching allocator that hands it out again at
+    // once: nothing of the library may still be running on it
+    if (c.device >= 0 && c.primes.p)
+        (void)hipDeviceSynchronize();
     c.primes.release();
     c.d_ctab.release();
     c.d_ptab.release();
@@ -633,31 +661,66 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
     return GB_OK;
 }
 
+// Device workspace of one launch sequence: where its kernels keep counters,
+// descriptors, segment records, spills and results (the library's own
+// buffers for gb_verify_range / gb_verify_batch).
+struct Ws {
+    GbCounters *ctr = nullptr;
+    unsigned long long *claims = nullptr;   // one queue head per round
+    GbIvDone *done = nullptr;
+    GbInterval *iv = nullptr;
+    GbSegRecord *rec = nullptr;
+    GbSpill *spill = nullptr;
+    uint64_t spill_cap = 0;
+    GbIvResult *res = nullptr;
+    uint64_t *unres = nullptr;
+    GbChunk *chunk = nullptr;
+    GbFillTask *task = nullptr;
+    uint32_t *bitmap = nullptr;
+};
+
+Ws library_ws(const Ctx &c)
+{
+    Ws w;
+    w.ctr = (GbCounters *)c.d_ctr.p;
+    w.claims = (unsigned long long *)c.d_claims.p;
+    w.done = (GbIvDone *)c.d_done.p;
+    w.iv = (GbInterval *)c.d_iv.p;
+    w.rec = (GbSegRecord *)c.d_rec.p;
+    w.spill = (GbSpill *)c.d_spill.p;
+    w.spill_cap = c.spill_cap;
+    w.res = (GbIvResult *)c.d_res.p;
+    w.unres = (uint64_t *)c.d_unres.p;
+    w.chunk = (GbChunk *)c.d_chunk.p;
+    w.task = (GbFillTask *)c.d_task.p;
+    w.bitmap = (uint32_t *)c.d_bitmap.p;
+    return w;
+}
+
 // The kernels of one verification, in stream order:
 //   reset -> per round: [bucket reset -> bucket fill ->] persistent
 //   sieve+probe -> Phase 2 -> reduce -> unresolved list.
 // Every kernel reads its sizes from device memory (counters, descriptors), so
 // the sequence needs no host round trip and can be captured as a graph.
 gb_status enqueue_kernels(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr,
-                          uint32_t grid, hipStream_t s, bool mark_probe)
+                          uint32_t grid, hipStream_t s, bool mark_probe, const Ws &w)
 {
     const uint64_t k = pl.iv.size();
-    GbCounters *ctr = (GbCounters *)c.d_ctr.p;
-    unsigned long long *claims = (unsigned long long *)c.d_claims.p;
-    GB_HIP(gb_launch_reset(ctr, (GbIvDone *)c.d_done.p, (uint32_t)k, claims,
-                           (uint32_t)pl.rounds.size(), s));
-    GB_HIP(gb_launch_chunk_roots((const uint32_t *)c.primes.p, c.nprimes, (GbChunk *)c.d_chunk.p,
+    GbCounters *ctr = w.ctr;
+    unsigned long long *claims = w.claims;
+    GB_HIP(gb_launch_reset(ctr, w.done, (uint32_t)k, claims, (uint32_t)pl.rounds.size(), s));
+    GB_HIP(gb_launch_chunk_roots((const uint32_t *)c.primes.p, c.nprimes, w.chunk,
                                  pl.chunks.size(), s));
     if (mark_probe)
         GB_HIP(hipEventRecord(c.ev[1], s));
     for (size_t ri = 0; ri < pl.rounds.size(); ++ri) {
         const Round &r = pl.rounds[ri];
         if (r.bm) {
-            GB_HIP(gb_launch_bucket_reset((uint32_t *)c.d_bitmap.p, r.nsegs * (uint64_t)pl.words, s));
+            GB_HIP(gb_launch_bucket_reset(w.bitmap, r.nsegs * (uint64_t)pl.words, s));
             GbBucketArgs b = {};
             b.primes = (const uint32_t *)c.primes.p;
-            b.chunk = (const GbChunk *)c.d_chunk.p + r.chunk_first;
-            b.task = (const GbFillTask *)c.d_task.p + r.task_first;
+            b.chunk = w.chunk + r.chunk_first;
+            b.task = w.task + r.task_first;
             b.ntask = (uint32_t)r.ntask;
             b.log2e = pr.seg_log2;
             b.H = pl.H;
@@ -665,27 +728,27 @@ gb_status enqueue_kernels(Ctx &c, const Plan &pl, uint64_t P_max, const gb_param
             b.wcu = pl.wcu;
             b.ntiles = r.ntiles;
             b.seg_base = r.seg_base;
-            b.bitmap = (uint32_t *)c.d_bitmap.p;
+            b.bitmap = w.bitmap;
             if (r.ntask && r.ntiles)
                 GB_HIP(gb_launch_bucket_fill(b, (uint32_t)std::min<uint64_t>(r.ntiles, 1u << 16), s));
         }
         GbProbeArgs a = {};
         a.primes = (const uint32_t *)c.primes.p;
         a.nprimes = c.nprimes;
-        a.iv = (const GbInterval *)c.d_iv.p;
+        a.iv = w.iv;
         a.k = (uint32_t)k;
         a.H = pl.H;
         a.ncand = pl.ncand;
         a.lb_count = r.bm ? pl.lb_count : (uint32_t)c.nprimes;
         a.seg_base = r.seg_base;
         a.nsegs = r.nsegs;
-        a.rec = (GbSegRecord *)c.d_rec.p;
-        a.spill = (GbSpill *)c.d_spill.p;
-        a.spill_cap = c.spill_cap;
+        a.rec = w.rec;
+        a.spill = w.spill;
+        a.spill_cap = w.spill_cap;
         a.ctr = ctr;
         a.claim = claims + ri;
-        a.done = (GbIvDone *)c.d_done.p;
-        a.bitmap = r.bm ? (const uint32_t *)c.d_bitmap.p : nullptr;
+        a.done = w.done;
+        a.bitmap = r.bm ? w.bitmap : nullptr;
         a.ctab = (const uint32_t *)c.d_ctab.p;
         a.ptab = (const uint32_t *)c.d_ptab.p;
         a.wcu = pl.wcu;
@@ -697,12 +760,10 @@ gb_status enqueue_kernels(Ctx &c, const Plan &pl, uint64_t P_max, const gb_param
     if (mark_probe)
         GB_HIP(hipEventRecord(c.ev[2], s));
     GB_HIP(gb_launch_phase2((const uint32_t *)c.primes.p, c.nprimes, (uint64_t)pl.ncand + 1,
-                            (GbSpill *)c.d_spill.p, c.spill_cap, ctr, (uint32_t)c.num_cu * 4, s));
-    GB_HIP(gb_launch_reduce((const GbInterval *)c.d_iv.p, (uint32_t)k, (const GbSegRecord *)c.d_rec.p,
-                            (const GbSpill *)c.d_spill.p, c.spill_cap, ctr, P_max,
-                            (GbIvResult *)c.d_res.p, s));
-    GB_HIP(gb_launch_unres_emit((const GbSpill *)c.d_spill.p, c.spill_cap, ctr, P_max,
-                                (uint64_t *)c.d_unres.p, (uint32_t)c.num_cu * 2, s));
+                            w.spill, w.spill_cap, ctr, (uint32_t)c.num_cu * 4, s));
+    GB_HIP(gb_launch_reduce(w.iv, (uint32_t)k, w.rec, w.spill, w.spill_cap, ctr, P_max, w.res, s));
+    GB_HIP(gb_launch_unres_emit(w.spill, w.spill_cap, ctr, P_max, w.unres,
+                                (uint32_t)c.num_cu * 2, s));
     return GB_OK;
 }
 
@@ -749,7 +810,7 @@ gb_status capture_graph(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params 
     if (!c.cap_stream)
         GB_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
     GB_HIP(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
-    gb_status st = enqueue_kernels(c, pl, P_max, pr, grid, c.cap_stream, false);
+    gb_status st = enqueue_kernels(c, pl, P_max, pr, grid, c.cap_stream, false, library_ws(c));
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(c.cap_stream, &graph);
     if (st != GB_OK) {
@@ -769,6 +830,23 @@ gb_status capture_graph(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params 
         return GB_EHIP;
     }
     c.graph_key = key;
+    return GB_OK;
+}
+
+// Persistent grid of the sieve+probe kernel: the workgroups that fit on the
+// device at once (or wg_per_cu per CU), never more than there are segments.
+gb_status probe_grid(const Ctx &c, const Plan &pl, const gb_params &pr, uint32_t *grid)
+{
+    *grid = 0;
+    if (pl.total_segs) {
+        int occ = 0;
+        GB_HIP(gb_probe_occupancy((int)pr.seg_log2, (int)pr.wg_size, &occ));
+        if (occ < 1)
+            occ = 1;
+        if (pr.wg_per_cu)
+            occ = std::min<int>(occ, (int)pr.wg_per_cu);
+        *grid = (uint32_t)std::min<uint64_t>(pl.total_segs, (uint64_t)c.num_cu * occ);
+    }
     return GB_OK;
 }
 
@@ -810,15 +888,7 @@ gb_status run_once_impl(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params 
             GB_HIP(hipEventCreate(&e));
 
     uint32_t grid = 0;
-    if (pl.total_segs) {
-        int occ = 0;
-        GB_HIP(gb_probe_occupancy((int)pr.seg_log2, (int)pr.wg_size, &occ));
-        if (occ < 1)
-            occ = 1;
-        if (pr.wg_per_cu)
-            occ = std::min<int>(occ, (int)pr.wg_per_cu);
-        grid = (uint32_t)std::min<uint64_t>(pl.total_segs, (uint64_t)c.num_cu * occ);
-    }
+    GB_TRY(probe_grid(c, pl, pr, &grid));
     std::memcpy(c.h_iv.p, pl.dev_iv.data(), k * sizeof(GbInterval));
     enqueued = true;
     GB_HIP(hipMemcpyAsync(c.d_iv.p, c.h_iv.p, k * sizeof(GbInterval), hipMemcpyHostToDevice, s));
@@ -838,7 +908,7 @@ gb_status run_once_impl(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params 
         GB_TRY(capture_graph(c, pl, P_max, pr, grid, key));
         GB_HIP(hipGraphLaunch(c.graph_exec, s));
     } else {
-        GB_TRY(enqueue_kernels(c, pl, P_max, pr, grid, s, true));
+        GB_TRY(enqueue_kernels(c, pl, P_max, pr, grid, s, true, library_ws(c)));
     }
     if (inject == 2) {
         set_err("failure injected after the kernels were enqueued (test hook)");
@@ -1023,6 +1093,25 @@ gb_status gb_verify_batch(const uint64_t *AB, uint64_t k, uint64_t P_max, void *
     std::lock_guard<std::mutex> lk(c.mu);
     g_err.clear();
     return verify_many(c, AB, k, P_max, (hipStream_t)stream, outs, true);
+}
+
+gb_status gb_set_allocator(gb_alloc_fn alloc, gb_free_fn free_, void *user)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    g_err.clear();
+    if ((alloc == nullptr) != (free_ == nullptr)) {
+        set_err("gb_set_allocator needs both functions, or neither (hipMalloc / hipFree)");
+        return GB_EINVAL;
+    }
+    if (c.device >= 0)
+        (void)hipSetDevice(c.device);
+    // every buffer goes back to the allocator that gave it
+    release_all(c);
+    g_alloc.alloc = alloc;
+    g_alloc.free_ = free_;
+    g_alloc.user = alloc ? user : nullptr;
+    return GB_OK;
 }
 
 gb_status gb_set_params(const gb_params *p)

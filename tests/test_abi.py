@@ -105,3 +105,11 @@ def test_failure_hook_validates_its_argument(gb):
     assert e.value.name == "GB_EINVAL"
     gb.debug_fail_next(1)
     gb.debug_fail_next(0)           # cleared again: nothing pending for later tests
+
+
+def test_set_allocator_validation(gb):
+    from paper_2603_07850_amd import _binding as b
+    L = gb.lib()
+    a = b.ALLOC_FN(lambda n, s, u: None)
+    assert L.gb_set_allocator(a, b.FREE_FN(), None) == 1          # GB_EINVAL: one of the two
+    assert L.gb_set_allocator(b.ALLOC_FN(), b.FREE_FN(), None) == 0
