@@ -161,6 +161,34 @@ gb_status gb_verify_batch(const uint64_t *AB, uint64_t k, uint64_t P_max,
                           void *stream, gb_result *outs);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * verification as gb_verify_range, with every scratch structure of the call
+ * (counters, descriptor, segment records, spill and unresolved lists) in a
+ * static 64 MiB device array that the library holds on each device from
+ * gb_base_primes() until the process ends.  The call makes no hipMalloc,
+ * hipFree or other allocating call; the caller passes `out` (and its
+ * unresolved buffer, host memory) as for gb_verify_range.
+ * Differences from gb_verify_range:
+ *  - every prime up to isqrt(B) is sieved inside the segments (no strike
+ *    bitmaps), so ranges near 2^64 run slower; results are identical;
+ *  - the range may span at most about 2.09 million segments of 2^seg_log2
+ *    evens (5.5e11 evens at seg_log2 = 18, 2.2e12 at 20): longer ranges fail
+ *    with GB_ENOMEM before anything is enqueued;
+ *  - the evens left open by the probe window share what the segment records
+ *    leave of the array; more than fit give GB_ENOMEM after the run (tiny
+ *    P_max over long ranges), and the result is then not written;
+ *  - gb_last_stats() and gb_last_latencies() are not updated.
+ * All calls on one device share its array and leave their contents in it.
+ * Calls are serialized by the library lock and each waits for its stream
+ * before returning, so two calls of one process never overlap on the array;
+ * work that overlapped on one GPU (for instance a kernel of the caller's
+ * still writing through an address it kept) would race.
+ */
+gb_status gb_verify_range_noalloc(uint64_t A, uint64_t B, uint64_t P_max, void *stream,
+                                  gb_result *out);
+
+/*
  * Test hook for the failure paths (Sec. 3.4, graceful error handling: an
  * error is reported, the library stays usable).  Makes the next
  * gb_verify_range / gb_verify_batch call fail with GB_EHIP at point `where`:

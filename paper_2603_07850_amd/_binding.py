@@ -90,6 +90,7 @@ def lib():
         "gb_table_read": (st, [vp, u64, u64]),
         "gb_verify_range": (st, [u64, u64, u64, vp, ctypes.POINTER(Result)]),
         "gb_verify_batch": (st, [vp, u64, u64, vp, vp]),
+        "gb_verify_range_noalloc": (st, [u64, u64, u64, vp, ctypes.POINTER(Result)]),
         "gb_set_allocator": (st, [ALLOC_FN, FREE_FN, vp]),
         "gb_set_params": (st, [ctypes.POINTER(Params)]),
         "gb_get_params": (st, [ctypes.POINTER(Params)]),
@@ -173,6 +174,21 @@ def verify_range(A, B, P_max, stream=None, unresolved_cap=1 << 16, allow_trunc=T
     r.unresolved = ctypes.cast(buf, ctypes.POINTER(ctypes.c_uint64))
     r.unresolved_cap = int(unresolved_cap)
     st = lib().gb_verify_range(int(A), int(B), int(P_max), _stream(stream), ctypes.byref(r))
+    _check(st, ok=(0, 5) if allow_trunc else (0,))
+    d = _to_dict(r, buf)
+    d["status"] = STATUS[st]
+    return d
+
+
+def verify_range_noalloc(A, B, P_max, stream=None, unresolved_cap=1 << 16, allow_trunc=True):
+    """gb_verify_range_noalloc: as verify_range, with the call's scratch in the
+    library's static device array (no device allocation)."""
+    buf = (ctypes.c_uint64 * max(int(unresolved_cap), 1))()
+    r = Result()
+    r.unresolved = ctypes.cast(buf, ctypes.POINTER(ctypes.c_uint64))
+    r.unresolved_cap = int(unresolved_cap)
+    st = lib().gb_verify_range_noalloc(int(A), int(B), int(P_max), _stream(stream),
+                                       ctypes.byref(r))
     _check(st, ok=(0, 5) if allow_trunc else (0,))
     d = _to_dict(r, buf)
     d["status"] = STATUS[st]

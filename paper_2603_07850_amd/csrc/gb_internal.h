@@ -159,6 +159,7 @@ uint32_t gb_table_seg_log2();
 
 hipError_t gb_launch_reset(GbCounters *ctr, GbIvDone *done, uint32_t k,
                            unsigned long long *claims, uint32_t nclaims, hipStream_t s);
+hipError_t gb_launch_put_interval(GbInterval *dst, const GbInterval &v, hipStream_t s);
 hipError_t gb_launch_pow2_counts(const uint32_t *primes, uint64_t nprimes, uint64_t *out33,
                                  hipStream_t s);
 hipError_t gb_launch_chunk_roots(const uint32_t *primes, uint64_t nprimes, GbChunk *chunks,

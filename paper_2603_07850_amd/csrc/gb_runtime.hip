@@ -24,7 +24,21 @@
 #include "goldbach.h"
 #include "gb_internal.h"
 
+// Scratch of gb_verify_range_noalloc: counters, the interval descriptor and
+// result, the segment records, the spill list and the unresolved list of one
+// call live in this file-scope device array, so that the call allocates
+// nothing.  Each device holds its own copy at its own address until the
+// process ends.  In host code the name `scratch` is a host-side stand-in, not
+// a device address: host code uses only the address hipGetSymbolAddress gives
+// for the current device (kept in g_scratch at gb_base_primes).
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+void *g_scratch[kMaxDevices] = {};   // device address of `scratch` per device (context lock)
+
 
 thread_local std::string g_err;
 
@@ -278,6 +292,22 @@ gb_status build_table(Ctx &c, uint64_t limit)
     hipDeviceProp_t prop;
     GB_HIP(hipGetDeviceProperties(&prop, dev));
     release_all(c);
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_err("device index %d is outside the supported 0..%d", dev, kMaxDevices - 1);
+        return GB_EINVAL;
+    }
+    if (!g_scratch[dev]) {
+        // once per device, with that device current
+        void *ptr = nullptr;
+        const hipError_t se = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (se != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            set_err("hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                    hipGetErrorString(se));
+            return GB_EHIP;
+        }
+        g_scratch[dev] = ptr;
+    }
     c.device = dev;
     c.num_cu = prop.multiProcessorCount;
     int khz = 0;
@@ -662,8 +692,9 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
 }
 
 // Device workspace of one launch sequence: where its kernels keep counters,
-// descriptors, segment records, spills and results (the library's own
-// buffers for gb_verify_range / gb_verify_batch).
+// descriptors, segment records, spills and results.  The library's own
+// buffers fill it for gb_verify_range / gb_verify_batch; the static scratch
+// array fills it for gb_verify_range_noalloc.
 struct Ws {
     GbCounters *ctr = nullptr;
     unsigned long long *claims = nullptr;   // one queue head per round
@@ -1026,6 +1057,107 @@ gb_status verify_many(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, hi
     return status;
 }
 
+// Layout of the scratch array for one call: fixed records at the start, then
+// the segment records, then the spill list and the unresolved list, which
+// share what the records leave.
+constexpr size_t kScrCtr = 0, kScrClaim = 64, kScrDone = 128, kScrIv = 256, kScrRes = 320;
+constexpr size_t kScrRec = 4096;
+constexpr uint64_t kScrMinSpill = 1024;
+
+gb_status verify_noalloc(Ctx &c, uint64_t A, uint64_t B, uint64_t P_max, hipStream_t s,
+                         gb_result *out)
+{
+    GB_TRY(use_device(c));
+    char *base = (char *)g_scratch[c.device];
+    if (!base) {
+        set_err("the no-alloc scratch of device %d was not set up", c.device);
+        return GB_ENOTABLE;
+    }
+    gb_params pr = c.params;
+    pr.bucket_log2 = 32;   // every prime is sieved inside the segment: no strike bitmaps
+    Plan pl;
+    const uint64_t AB[2] = {A, B};
+    GB_TRY(make_plan(c, AB, 1, P_max, pr, pl));
+    const uint64_t rec_bytes = (pl.total_segs * sizeof(GbSegRecord) + 255) / 256 * 256;
+    const uint64_t left = kScratchBytes - kScrRec >= rec_bytes ? kScratchBytes - kScrRec - rec_bytes : 0;
+    const uint64_t spill_cap = left / (sizeof(GbSpill) + sizeof(uint64_t));
+    if (spill_cap < kScrMinSpill) {
+        set_err("range of %llu segments needs %llu bytes of segment records; the no-alloc "
+                "scratch holds %llu bytes (at most %llu segments of 2^%u evens)",
+                (unsigned long long)pl.total_segs, (unsigned long long)rec_bytes,
+                (unsigned long long)kScratchBytes,
+                (unsigned long long)((kScratchBytes - kScrRec - kScrMinSpill * 24) / sizeof(GbSegRecord)),
+                pr.seg_log2);
+        return GB_ENOMEM;
+    }
+    Ws w;
+    w.ctr = (GbCounters *)(base + kScrCtr);
+    w.claims = (unsigned long long *)(base + kScrClaim);
+    w.done = (GbIvDone *)(base + kScrDone);
+    w.iv = (GbInterval *)(base + kScrIv);
+    w.res = (GbIvResult *)(base + kScrRes);
+    w.rec = (GbSegRecord *)(base + kScrRec);
+    w.spill = (GbSpill *)(base + kScrRec + rec_bytes);
+    w.spill_cap = spill_cap;
+    w.unres = (uint64_t *)(base + kScrRec + rec_bytes + spill_cap * sizeof(GbSpill));
+    uint32_t grid = 0;
+    GB_TRY(probe_grid(c, pl, pr, &grid));
+    // the descriptor goes in as a kernel argument: no host staging buffer
+    hipError_t e = gb_launch_put_interval(w.iv, pl.dev_iv[0], s);
+    gb_status st = GB_OK;
+    if (e != hipSuccess) {
+        set_err("descriptor upload failed: %s", hipGetErrorString(e));
+        st = GB_EHIP;
+    }
+    if (st == GB_OK)
+        st = enqueue_kernels(c, pl, P_max, pr, grid, s, false, w);
+    GbIvResult r = {};
+    GbCounters hc = {};
+    if (st == GB_OK) {
+        e = hipMemcpyAsync(&r, w.res, sizeof r, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&hc, w.ctr, sizeof hc, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) {
+            set_err("result copy failed: %s", hipGetErrorString(e));
+            st = GB_EHIP;
+        }
+    }
+    // nothing of this call may still run when it returns
+    e = hipStreamSynchronize(s);
+    if (st != GB_OK)
+        return st;
+    if (e != hipSuccess) {
+        set_err("stream synchronization failed: %s", hipGetErrorString(e));
+        return GB_EHIP;
+    }
+    if (hc.spills > spill_cap) {
+        set_err("%llu evens left open by the probe window exceed the %llu spill entries the "
+                "no-alloc scratch holds for this range (gb_verify_range has no such limit)",
+                (unsigned long long)hc.spills, (unsigned long long)spill_cap);
+        return GB_ENOMEM;
+    }
+    out->A = pl.An[0];
+    out->B = pl.Bn[0];
+    out->P_max = P_max;
+    out->verified = r.verified;
+    out->max_p = r.max_p;
+    out->max_p_n = r.max_p_n;
+    out->checksum = r.checksum;
+    out->n_unresolved = r.n_unresolved;
+    out->n_failed = r.n_failed;
+    if (r.n_unresolved) {
+        const uint64_t take = std::min<uint64_t>(r.n_unresolved, out->unresolved ? out->unresolved_cap : 0);
+        if (take)
+            GB_HIP(hipMemcpy(out->unresolved, w.unres + r.unres_first, take * 8, hipMemcpyDeviceToHost));
+        if (take < r.n_unresolved) {
+            set_err("unresolved list truncated (%llu > %llu)", (unsigned long long)r.n_unresolved,
+                    (unsigned long long)take);
+            return GB_ETRUNC;
+        }
+    }
+    return GB_OK;
+}
+
 }  // namespace
 
 void gb_internal_set_error(const char *msg) { g_err = msg ? msg : ""; }
@@ -1093,6 +1225,19 @@ gb_status gb_verify_batch(const uint64_t *AB, uint64_t k, uint64_t P_max, void *
     std::lock_guard<std::mutex> lk(c.mu);
     g_err.clear();
     return verify_many(c, AB, k, P_max, (hipStream_t)stream, outs, true);
+}
+
+gb_status gb_verify_range_noalloc(uint64_t A, uint64_t B, uint64_t P_max, void *stream,
+                                  gb_result *out)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    g_err.clear();
+    if (!out) {
+        set_err("null result");
+        return GB_EINVAL;
+    }
+    return verify_noalloc(c, A, B, P_max, (hipStream_t)stream, out);
 }
 
 gb_status gb_set_allocator(gb_alloc_fn alloc, gb_free_fn free_, void *user)

@@ -955,6 +955,14 @@ __global__ void reset_kernel(GbCounters *ctr, GbIvDone *done, uint32_t k,
     }
 }
 
+// One interval descriptor written from a kernel argument (a launch with no
+// host staging buffer).
+__global__ void put_interval_kernel(GbInterval *dst, GbInterval v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *dst = v;
+}
+
 // Number of table primes <= 2^j for j = 0..32 (the planner's bucket bounds).
 __global__ void pow2_counts_kernel(const uint32_t *primes, uint64_t nprimes, uint64_t *out)
 {
@@ -1015,6 +1023,12 @@ hipError_t gb_launch_reset(GbCounters *ctr, GbIvDone *done, uint32_t k,
 {
     const uint32_t blocks = k > 256 * 64 ? 64 : (k + 255) / 256 + 1;
     hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, ctr, done, k, claims, nclaims);
+    return hipGetLastError();
+}
+
+hipError_t gb_launch_put_interval(GbInterval *dst, const GbInterval &v, hipStream_t s)
+{
+    hipLaunchKernelGGL(put_interval_kernel, dim3(1), dim3(64), 0, s, dst, v);
     return hipGetLastError();
 }
 

@@ -113,3 +113,11 @@ def test_set_allocator_validation(gb):
     a = b.ALLOC_FN(lambda n, s, u: None)
     assert L.gb_set_allocator(a, b.FREE_FN(), None) == 1          # GB_EINVAL: one of the two
     assert L.gb_set_allocator(b.ALLOC_FN(), b.FREE_FN(), None) == 0
+
+
+def test_noalloc_without_table_is_reported(gb):
+    gb.release()
+    with pytest.raises(gb.GoldbachError) as e:
+        gb.verify_range_noalloc(4, 100, 100)
+    assert e.value.name == "GB_ENOTABLE"
+
