@@ -161,6 +161,54 @@ gb_status gb_verify_batch(const uint64_t *AB, uint64_t k, uint64_t P_max,
                           void *stream, gb_result *outs);
 
 /*
+ * Verification past 2^64 (paper Sec. 5, future work "pushing past the 64-bit
+ * ceiling": 128-bit sieve arithmetic coupled with a Baillie-PSW test).
+ * Bounds and n are unsigned 128-bit integers given as (lo, hi) halves.  Up to
+ * 2^64 nothing changes: p_min(n) = min { p prime : n - p prime }, and the part
+ * of [A, B] below 2^64 goes through gb_verify_range.  From 2^64 on no prime
+ * table reaches sqrt(n - p), so primality of q = n - p is decided by the
+ * Baillie-PSW test (a strong probable-prime test to base 2 and a strong Lucas
+ * test with Selfridge's parameters; no composite passing it is known):
+ *     p_min(n) = min { p prime : n - p passes Baillie-PSW }.
+ * The segment window, sieved in LDS by the table primes up to
+ * min(T, 2^28) with 128-bit offsets, only removes q with small factors; the
+ * survivors are tested in ascending p.  P_max and Phase 2 as in
+ * gb_verify_range (Phase 2 tests table primes above P_max by Baillie-PSW).
+ *   A, B   any u128 pair (normalized inward to even numbers, A raised to 4;
+ *          B = 2^128 - 1 rounds to 2^128 - 2).  At most 2^40 evens at or
+ *          above 2^64 per call (GB_EINVAL).  No isqrt(B) condition on the
+ *          table limit T beyond the 64-bit part.
+ *   out    caller-owned; out->unresolved holds 2 * unresolved_cap u64, the
+ *          (lo, hi) halves of each unresolved n in ascending order.
+ * Errors as gb_verify_range; GB_ENOMEM when more than 65536 evens at or above
+ * 2^64 are left open by P_max (a tiny P_max over a long range).  Blocks until
+ * done.  gb_last_stats() describes the wide kernel's launch.
+ */
+typedef struct gb_result128 {
+    uint64_t A_lo, A_hi, B_lo, B_hi;
+    uint64_t P_max;
+    uint64_t verified;
+    uint64_t max_p;
+    uint64_t max_p_n_lo, max_p_n_hi;
+    uint64_t checksum;
+    uint64_t n_unresolved;
+    uint64_t n_failed;
+    uint64_t *unresolved;
+    uint64_t unresolved_cap;
+} gb_result128;
+
+gb_status gb_verify_range_u128(uint64_t A_lo, uint64_t A_hi, uint64_t B_lo, uint64_t B_hi,
+                               uint64_t P_max, void *stream, gb_result128 *out);
+
+/*
+ * Primality of `count` u128 values q[2i] + 2^64 q[2i+1] (DEVICE pointers:
+ * 16 * count and count bytes): the deterministic Miller-Rabin test below 2^64
+ * and Baillie-PSW above, the tests of gb_verify_range_u128, exported so that
+ * they can be checked on their own.
+ */
+gb_status gb_is_prime_u128(const uint64_t *q, uint64_t count, uint8_t *is_prime, void *stream);
+
+/*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * verification as gb_verify_range, with every scratch structure of the call

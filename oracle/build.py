@@ -7,13 +7,13 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "gb_oracle.c")
+SRCS = [os.path.join(HERE, "gb_oracle.c"), os.path.join(HERE, "gb_oracle_wide.c")]
 OUT = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose=False):
     cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-shared", "-fPIC",
-           "-o", OUT + ".tmp", SRC]
+           "-o", OUT + ".tmp"] + SRCS
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -25,6 +25,12 @@ class OracleResult(ctypes.Structure):
     ]
 
 
+class OracleResultWide(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in (
+        "A_lo", "A_hi", "B_lo", "B_hi", "P_max", "verified", "max_p", "max_p_n_lo",
+        "max_p_n_hi", "checksum", "n_unresolved", "n_failed")]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -45,6 +51,13 @@ def lib():
         L.gbo_is_prime_window.restype = None
         L.gbo_sieve_window.argtypes = [u64, u64, p, u64, u64, p]
         L.gbo_sieve_window.restype = ctypes.c_int
+        L.gbo_bpsw.argtypes = [u64, u64]
+        L.gbo_bpsw.restype = ctypes.c_int
+        L.gbo_isqrt128.argtypes = [u64, u64]
+        L.gbo_isqrt128.restype = u64
+        L.gbo_verify_range_wide.argtypes = [u64, u64, u64, u64, u64, p, u64, u64,
+                                            ctypes.POINTER(OracleResultWide), p, u64, p]
+        L.gbo_verify_range_wide.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -145,4 +158,51 @@ def merge(a, b):
     out["unresolved"] = list(a.get("unresolved", [])) + list(b.get("unresolved", []))
     if (b["max_p"], -b["max_p_n"]) > (a["max_p"], -a["max_p_n"]):
         out["max_p"], out["max_p_n"] = b["max_p"], b["max_p_n"]
+    return out
+
+
+M64 = (1 << 64) - 1
+
+
+def bpsw(q):
+    """Baillie-PSW probable-primality of 0 <= q < 2^128 - 1 (gb_oracle_wide.c)."""
+    q = int(q)
+    return bool(lib().gbo_bpsw(q & M64, q >> 64))
+
+
+def isqrt128(x):
+    x = int(x)
+    return int(lib().gbo_isqrt128(x & M64, x >> 64))
+
+
+def verify_range_wide(A, B, P_max, limit, cap=1 << 12, want_pmin=False):
+    """Aggregates of every even n in the u128 range [A, B] with primality of
+    n - p decided by BPSW (gb_oracle_wide.c); unresolved n as Python ints."""
+    T = table_limit(limit)
+    tab = primes(T)
+    res = OracleResultWide()
+    unres = np.zeros(2 * max(cap, 1), dtype=np.uint64)
+    A, B = int(A), int(B)
+    pmin = None
+    if want_pmin:
+        a = max(4, A + (A & 1))
+        n = (B - (B & 1) - a) // 2 + 1 if B - (B & 1) >= a else 0
+        if n > 1 << 24:
+            raise ValueError("want_pmin is for short ranges")
+        pmin = np.zeros(max(n, 1), dtype=np.uint32)
+    st = lib().gbo_verify_range_wide(A & M64, A >> 64, B & M64, B >> 64, int(P_max),
+                                     tab.ctypes.data, len(tab), T, ctypes.byref(res),
+                                     unres.ctypes.data, cap,
+                                     pmin.ctypes.data if pmin is not None else None)
+    out = {
+        "A": res.A_lo | (res.A_hi << 64), "B": res.B_lo | (res.B_hi << 64),
+        "P_max": int(res.P_max), "verified": int(res.verified), "max_p": int(res.max_p),
+        "max_p_n": res.max_p_n_lo | (res.max_p_n_hi << 64), "checksum": int(res.checksum),
+        "n_unresolved": int(res.n_unresolved), "n_failed": int(res.n_failed),
+        "status": int(st),
+    }
+    k = min(out["n_unresolved"], cap)
+    out["unresolved"] = [int(unres[2 * i]) | (int(unres[2 * i + 1]) << 64) for i in range(k)]
+    if want_pmin:
+        out["pmin"] = pmin[:(out["B"] - out["A"]) // 2 + 1] if out["B"] >= out["A"] else pmin[:0]
     return out

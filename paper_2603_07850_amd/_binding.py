@@ -31,6 +31,13 @@ class Result(ctypes.Structure):
     ]
 
 
+class Result128(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in (
+        "A_lo", "A_hi", "B_lo", "B_hi", "P_max", "verified", "max_p", "max_p_n_lo",
+        "max_p_n_hi", "checksum", "n_unresolved", "n_failed")] + \
+        [("unresolved", ctypes.POINTER(ctypes.c_uint64)), ("unresolved_cap", ctypes.c_uint64)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("seg_log2", ctypes.c_uint32), ("wg_size", ctypes.c_uint32),
                 ("window", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32),
@@ -91,6 +98,8 @@ def lib():
         "gb_verify_range": (st, [u64, u64, u64, vp, ctypes.POINTER(Result)]),
         "gb_verify_batch": (st, [vp, u64, u64, vp, vp]),
         "gb_verify_range_noalloc": (st, [u64, u64, u64, vp, ctypes.POINTER(Result)]),
+        "gb_verify_range_u128": (st, [u64, u64, u64, u64, u64, vp, ctypes.POINTER(Result128)]),
+        "gb_is_prime_u128": (st, [vp, u64, vp, vp]),
         "gb_set_allocator": (st, [ALLOC_FN, FREE_FN, vp]),
         "gb_set_params": (st, [ctypes.POINTER(Params)]),
         "gb_get_params": (st, [ctypes.POINTER(Params)]),
@@ -193,6 +202,43 @@ def verify_range_noalloc(A, B, P_max, stream=None, unresolved_cap=1 << 16, allow
     d = _to_dict(r, buf)
     d["status"] = STATUS[st]
     return d
+
+
+M64 = (1 << 64) - 1
+
+
+def verify_range_u128(A, B, P_max, stream=None, unresolved_cap=1 << 12, allow_trunc=True):
+    """gb_verify_range_u128: every even n in the u128 range [A, B]; past 2^64
+    primality of n - p is decided by Baillie-PSW.  Python ints in and out."""
+    A, B = int(A), int(B)
+    buf = (ctypes.c_uint64 * (2 * max(int(unresolved_cap), 1)))()
+    r = Result128()
+    r.unresolved = ctypes.cast(buf, ctypes.POINTER(ctypes.c_uint64))
+    r.unresolved_cap = int(unresolved_cap)
+    st = lib().gb_verify_range_u128(A & M64, A >> 64, B & M64, B >> 64, int(P_max),
+                                    _stream(stream), ctypes.byref(r))
+    _check(st, ok=(0, 5) if allow_trunc else (0,))
+    d = {"A": r.A_lo | (r.A_hi << 64), "B": r.B_lo | (r.B_hi << 64), "P_max": int(r.P_max),
+         "verified": int(r.verified), "max_p": int(r.max_p),
+         "max_p_n": r.max_p_n_lo | (r.max_p_n_hi << 64), "checksum": int(r.checksum),
+         "n_unresolved": int(r.n_unresolved), "n_failed": int(r.n_failed)}
+    take = min(d["n_unresolved"], int(unresolved_cap))
+    d["unresolved"] = [int(buf[2 * i]) | (int(buf[2 * i + 1]) << 64) for i in range(take)]
+    d["status"] = STATUS[st]
+    return d
+
+
+def is_prime_u128(values):
+    """Device primality (Miller-Rabin below 2^64, Baillie-PSW above) of a list
+    of Python ints below 2^128; returns a list of bools."""
+    import numpy as np
+    import torch
+    v = np.array([[int(x) & M64, int(x) >> 64] for x in values], dtype=np.uint64).reshape(-1)
+    q = torch.tensor(v.view(np.int64), device="cuda")
+    out = torch.empty(len(values), dtype=torch.uint8, device="cuda")
+    _check(lib().gb_is_prime_u128(q.data_ptr(), len(values), out.data_ptr(),
+                                  torch.cuda.current_stream().cuda_stream))
+    return [bool(x) for x in out.cpu().tolist()]
 
 
 def verify_batch(intervals, P_max, stream=None, unresolved_cap=1024, allow_trunc=True):
@@ -332,55 +378,6 @@ def use_torch_allocator(device=None):
 
     set_allocator(alloc, free)
     return count
-
-
-class Server:
-    """Served form: continuous batching of submitted ranges (gb_server_*)."""
-
-    def __init__(self, P_max, hbm_budget_bytes=64 << 30, max_active=64, piece_segments=256,
-                 max_pending=0):
-        cfg = ServerConfig(int(hbm_budget_bytes), int(P_max), int(max_active),
-                           int(piece_segments), int(max_pending), 0)
-        self._h = ctypes.c_void_p()
-        _check(lib().gb_server_open(ctypes.byref(cfg), ctypes.byref(self._h)))
-        self.P_max = int(P_max)
-
-    def submit(self, A, B):
-        rid = ctypes.c_uint64()
-        _check(lib().gb_server_submit(self._h, int(A), int(B), ctypes.byref(rid)))
-        return int(rid.value)
-
-    def poll(self, wait_ms=-1, unresolved_cap=1024):
-        """(id, result dict, latency seconds), or None if nothing finished in time."""
-        buf = (ctypes.c_uint64 * max(int(unresolved_cap), 1))()
-        r = Result()
-        r.unresolved = ctypes.cast(buf, ctypes.POINTER(ctypes.c_uint64))
-        r.unresolved_cap = int(unresolved_cap)
-        rid = ctypes.c_uint64()
-        lat = ctypes.c_double()
-        st = lib().gb_server_poll(self._h, int(wait_ms), ctypes.byref(rid), ctypes.byref(r),
-                                  ctypes.byref(lat))
-        if st == 7:
-            return None
-        _check(st, ok=(0, 5))
-        return int(rid.value), _to_dict(r, buf), lat.value / 1e3
-
-    def stats(self):
-        s = ServerStats()
-        _check(lib().gb_server_get_stats(self._h, ctypes.byref(s)))
-        return {f: (float(getattr(s, f)) if f.endswith("_ms") else int(getattr(s, f)))
-                for f, _ in ServerStats._fields_}
-
-    def close(self):
-        if self._h:
-            _check(lib().gb_server_close(self._h))
-            self._h = ctypes.c_void_p()
-
-    def __enter__(self):
-        return self
-
-    def __exit__(self, *exc):
-        self.close()
 
 
 class Server:

@@ -144,6 +144,62 @@ struct GbBucketArgs {
     uint32_t wcu;         // class-array words per segment bitmap (three per segment)
 };
 
+// ---- verification past 2^64 (gb_wide.hip) ----
+
+// An unsigned 128-bit integer as two 64-bit words.
+struct u128w {
+    uint64_t lo, hi;
+};
+
+// Partial aggregates of one wide segment.
+struct GbWideRecord {
+    uint64_t checksum;
+    uint64_t verified;
+    uint64_t max_p;
+    uint64_t max_n_lo, max_n_hi;   // smallest n attaining max_p (0 if none)
+    uint64_t nspill;
+    uint64_t pad[2];
+};
+
+// An even past 2^64 that the candidates p <= P_max left open; p is set by the
+// wide Phase-2 kernel (0: none found).
+struct GbWideSpill {
+    uint64_t n_lo, n_hi;
+    uint64_t p;
+    uint64_t pad;
+};
+
+struct GbWideResult {
+    uint64_t verified, checksum, max_p, max_n_lo, max_n_hi, n_unresolved, n_failed, spills;
+};
+
+struct GbWideArgs {
+    const uint32_t *primes;
+    uint64_t nprimes;
+    uint32_t nsieve;      // primes[1 .. nsieve) are sieved out of every window
+    uint32_t ncand;       // candidates primes[1 .. ncand]
+    uint32_t H;           // halo bits: (largest candidate - 1) / 2, rounded up to 32
+    uint32_t pad;
+    u128w A;              // first even of the range
+    uint64_t nE;          // evens of the range
+    uint64_t nsegs;
+    GbWideRecord *rec;
+    GbWideSpill *spill;
+    uint64_t spill_cap;
+    unsigned long long *ctr;   // [0] segment claims, [1] spills appended
+};
+
+constexpr int kWideLog2E = 16;     // evens per wide segment
+constexpr int kWideThreads = 256;
+
+hipError_t gb_launch_wide(const GbWideArgs &a, uint32_t grid, hipStream_t s);
+int gb_wide_occupancy();
+hipError_t gb_launch_wide_phase2(const GbWideArgs &a, uint32_t grid, hipStream_t s);
+hipError_t gb_launch_wide_reduce(const GbWideArgs &a, uint64_t P_max, GbWideResult *res,
+                                 u128w *unres, hipStream_t s);
+hipError_t gb_launch_wide_reset(unsigned long long *ctr, hipStream_t s);
+hipError_t gb_launch_bpsw(const u128w *q, uint64_t count, uint8_t *out, hipStream_t s);
+
 // Set the calling thread's gb_last_error() message (host code).
 void gb_internal_set_error(const char *msg);
 

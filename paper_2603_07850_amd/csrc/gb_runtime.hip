@@ -178,6 +178,9 @@ struct Ctx {
     DevBuf d_bitmap, d_chunk, d_claims, d_task;
     HostBuf h_chunk, h_task;
     std::vector<uint64_t> last_slot;    // last call: caller's index -> kernel slot
+    // workspaces of the verification past 2^64
+    DevBuf d_wrec, d_wspill, d_wres, d_wunres, d_wctr;
+    HostBuf h_wres;
 };
 
 Ctx &ctx()
@@ -274,6 +277,12 @@ void release_all(Ctx &c)
     c.h_iv.release();
     c.h_res.release();
     c.h_ctr.release();
+    c.d_wrec.release();
+    c.d_wspill.release();
+    c.d_wres.release();
+    c.d_wunres.release();
+    c.d_wctr.release();
+    c.h_wres.release();
     c.small.clear();
     for (auto &e : c.ev)
         if (e) {
@@ -1158,6 +1167,213 @@ gb_status verify_noalloc(Ctx &c, uint64_t A, uint64_t B, uint64_t P_max, hipStre
     return GB_OK;
 }
 
+// ---- verification past 2^64 ----
+
+typedef unsigned __int128 u128h;   // host-side 128-bit integers
+
+u128h to_u128(uint64_t lo, uint64_t hi) { return ((u128h)hi << 64) | lo; }
+
+constexpr uint64_t kWideSpillCap = 1ull << 16;   // the reduce ranks spills pairwise
+constexpr uint64_t kWideMaxEvens = 1ull << 40;
+constexpr uint32_t kWideSieveLog2 = 28;           // sieve bound S = min(T, 2^28)
+
+// Every even of [A, B] with A >= 2^64 (normalized, A <= B), by the wide
+// kernels; fields of *out other than the unresolved buffer are written.
+gb_status verify_wide_part(Ctx &c, u128h A, u128h B, uint64_t P_max, hipStream_t s,
+                           gb_result128 *out, std::vector<u128h> &unres)
+{
+    const u128h nE128 = (B - A) / 2 + 1;
+    if (nE128 > kWideMaxEvens) {
+        set_err("a range past 2^64 may hold at most 2^40 evens per call");
+        return GB_EINVAL;
+    }
+    const uint64_t nE = (uint64_t)nE128;
+    const uint64_t pc = std::min<uint64_t>(P_max, 65536);
+    const uint64_t nc = small_count_le(c, pc);
+    const uint32_t ncand = (uint32_t)(nc > 0 ? nc - 1 : 0);
+    const uint32_t hmax = ncand ? (c.small[ncand] - 1) / 2 : 0;
+    const uint32_t H = std::max<uint32_t>(32, (hmax + 31) / 32 * 32);
+    const uint64_t nsieve = c.T >= (1ull << kWideSieveLog2) ? c.pi2[kWideSieveLog2] : c.nprimes;
+    const uint64_t nsegs = (nE + (1ull << kWideLog2E) - 1) >> kWideLog2E;
+    GB_TRY(c.d_wrec.reserve(nsegs * sizeof(GbWideRecord)));
+    GB_TRY(c.d_wspill.reserve(kWideSpillCap * sizeof(GbWideSpill)));
+    GB_TRY(c.d_wunres.reserve(kWideSpillCap * sizeof(u128w)));
+    GB_TRY(c.d_wres.reserve(sizeof(GbWideResult)));
+    GB_TRY(c.d_wctr.reserve(64));
+    GB_TRY(c.h_wres.reserve(sizeof(GbWideResult)));
+    for (auto &e : c.ev)
+        if (!e)
+            GB_HIP(hipEventCreate(&e));
+    GbWideArgs a = {};
+    a.primes = (const uint32_t *)c.primes.p;
+    a.nprimes = c.nprimes;
+    a.nsieve = (uint32_t)nsieve;
+    a.ncand = ncand;
+    a.H = H;
+    a.A.lo = (uint64_t)A;
+    a.A.hi = (uint64_t)(A >> 64);
+    a.nE = nE;
+    a.nsegs = nsegs;
+    a.rec = (GbWideRecord *)c.d_wrec.p;
+    a.spill = (GbWideSpill *)c.d_wspill.p;
+    a.spill_cap = kWideSpillCap;
+    a.ctr = (unsigned long long *)c.d_wctr.p;
+    const uint32_t grid =
+        (uint32_t)std::min<uint64_t>(nsegs, (uint64_t)c.num_cu * (uint64_t)gb_wide_occupancy());
+    gb_status st = GB_OK;
+    auto launch = [&]() -> gb_status {
+        GB_HIP(hipEventRecord(c.ev[0], s));
+        GB_HIP(gb_launch_wide_reset(a.ctr, s));
+        GB_HIP(hipEventRecord(c.ev[1], s));
+        GB_HIP(gb_launch_wide(a, grid, s));
+        GB_HIP(hipEventRecord(c.ev[2], s));
+        GB_HIP(gb_launch_wide_phase2(a, (uint32_t)c.num_cu * 4, s));
+        GB_HIP(gb_launch_wide_reduce(a, P_max, (GbWideResult *)c.d_wres.p, (u128w *)c.d_wunres.p, s));
+        GB_HIP(hipMemcpyAsync(c.h_wres.p, c.d_wres.p, sizeof(GbWideResult), hipMemcpyDeviceToHost, s));
+        GB_HIP(hipEventRecord(c.ev[3], s));
+        return GB_OK;
+    };
+    st = launch();
+    const hipError_t se = hipStreamSynchronize(s);
+    if (st != GB_OK)
+        return st;
+    GB_HIP(se);
+    const GbWideResult &r = *(const GbWideResult *)c.h_wres.p;
+    if (r.spills > kWideSpillCap) {
+        set_err("%llu evens past 2^64 were left open by the candidates p <= %llu; at most %llu "
+                "are supported per call (raise P_max or split the range)",
+                (unsigned long long)r.spills, (unsigned long long)P_max,
+                (unsigned long long)kWideSpillCap);
+        return GB_ENOMEM;
+    }
+    float tot = 0, pm = 0;
+    GB_HIP(hipEventElapsedTime(&tot, c.ev[0], c.ev[3]));
+    GB_HIP(hipEventElapsedTime(&pm, c.ev[1], c.ev[2]));
+    gb_stats &stt = c.stats;
+    stt = gb_stats{};
+    stt.probe_ms = pm;
+    stt.total_ms = tot;
+    stt.segments = nsegs;
+    stt.evens = nE;
+    stt.spills = r.spills;
+    stt.grid = grid;
+    stt.wg_size = kWideThreads;
+    stt.seg_log2 = kWideLog2E;
+    stt.halo_bits = H;
+    stt.ncand = ncand;
+    stt.intervals = 1;
+    c.last_k = 0;
+    out->verified = r.verified;
+    out->checksum = r.checksum;
+    out->max_p = r.max_p;
+    out->max_p_n_lo = r.max_n_lo;
+    out->max_p_n_hi = r.max_n_hi;
+    out->n_unresolved = r.n_unresolved;
+    out->n_failed = r.n_failed;
+    unres.clear();
+    if (r.n_unresolved) {
+        std::vector<u128w> tmp(r.n_unresolved);
+        GB_HIP(hipMemcpy(tmp.data(), c.d_wunres.p, r.n_unresolved * sizeof(u128w),
+                         hipMemcpyDeviceToHost));
+        for (const u128w &v : tmp)
+            unres.push_back(to_u128(v.lo, v.hi));
+    }
+    return GB_OK;
+}
+
+gb_status verify_u128(Ctx &c, u128h A, u128h B, uint64_t P_max, hipStream_t s, gb_result128 *out)
+{
+    GB_TRY(use_device(c));
+    if (P_max < 2) {
+        set_err("P_max must be >= 2 (got %llu)", (unsigned long long)P_max);
+        return GB_EINVAL;
+    }
+    if (P_max > c.T) {
+        set_err("P_max %llu exceeds the prime table limit %llu", (unsigned long long)P_max,
+                (unsigned long long)c.T);
+        return GB_ERANGE;
+    }
+    const u128h top = ~(u128h)0;
+    gb_result128 r = {};
+    r.P_max = P_max;
+    bool empty = false;
+    if (A & 1) {
+        if (A == top)
+            empty = true;
+        else
+            A += 1;
+    }
+    if (A < 4)
+        A = 4;
+    B &= ~(u128h)1;
+    r.A_lo = empty ? ~0ull : (uint64_t)A;
+    r.A_hi = empty ? ~0ull : (uint64_t)(A >> 64);
+    r.B_lo = (uint64_t)B;
+    r.B_hi = (uint64_t)(B >> 64);
+    std::vector<u128h> list;
+    gb_status status = GB_OK;
+    if (!empty && A <= B) {
+        const u128h two64 = (u128h)1 << 64;
+        if (A < two64) {
+            // the part below 2^64 goes through the 64-bit path
+            const uint64_t b64 = B < two64 ? (uint64_t)B : ~1ull;   // 2^64 - 2
+            std::vector<uint64_t> lo_list(1 << 16);
+            gb_result lr = {};
+            lr.unresolved = lo_list.data();
+            lr.unresolved_cap = lo_list.size();
+            const uint64_t AB[2] = {(uint64_t)A, b64};
+            gb_status ls = verify_many(c, AB, 1, P_max, s, &lr, false);
+            if (ls == GB_ETRUNC) {
+                lo_list.resize(lr.n_unresolved);
+                lr.unresolved = lo_list.data();
+                lr.unresolved_cap = lo_list.size();
+                ls = verify_many(c, AB, 1, P_max, s, &lr, false);
+            }
+            GB_TRY(ls);
+            r.verified = lr.verified;
+            r.checksum = lr.checksum;
+            r.max_p = lr.max_p;
+            r.max_p_n_lo = lr.max_p_n;
+            r.max_p_n_hi = 0;
+            r.n_unresolved = lr.n_unresolved;
+            r.n_failed = lr.n_failed;
+            for (uint64_t i = 0; i < lr.n_unresolved; ++i)
+                list.push_back(lo_list[i]);
+        }
+        if (B >= two64) {
+            const u128h a2 = A < two64 ? two64 : A;
+            gb_result128 hr = {};
+            std::vector<u128h> hl;
+            GB_TRY(verify_wide_part(c, a2, B, P_max, s, &hr, hl));
+            // merge: the high part's evens all lie above the low part's
+            r.verified += hr.verified;
+            r.checksum += hr.checksum;
+            if (hr.max_p > r.max_p) {
+                r.max_p = hr.max_p;
+                r.max_p_n_lo = hr.max_p_n_lo;
+                r.max_p_n_hi = hr.max_p_n_hi;
+            }
+            r.n_unresolved += hr.n_unresolved;
+            r.n_failed += hr.n_failed;
+            list.insert(list.end(), hl.begin(), hl.end());
+        }
+    }
+    const uint64_t take = std::min<uint64_t>(list.size(), out->unresolved ? out->unresolved_cap : 0);
+    for (uint64_t i = 0; i < take; ++i) {
+        out->unresolved[2 * i] = (uint64_t)list[i];
+        out->unresolved[2 * i + 1] = (uint64_t)(list[i] >> 64);
+    }
+    if (take < list.size()) {
+        status = GB_ETRUNC;
+        set_err("unresolved list truncated (%llu > %llu)", (unsigned long long)list.size(),
+                (unsigned long long)take);
+    }
+    r.unresolved = out->unresolved;
+    r.unresolved_cap = out->unresolved_cap;
+    *out = r;
+    return status;
+}
+
 }  // namespace
 
 void gb_internal_set_error(const char *msg) { g_err = msg ? msg : ""; }
@@ -1238,6 +1454,35 @@ gb_status gb_verify_range_noalloc(uint64_t A, uint64_t B, uint64_t P_max, void *
         return GB_EINVAL;
     }
     return verify_noalloc(c, A, B, P_max, (hipStream_t)stream, out);
+}
+
+gb_status gb_verify_range_u128(uint64_t A_lo, uint64_t A_hi, uint64_t B_lo, uint64_t B_hi,
+                               uint64_t P_max, void *stream, gb_result128 *out)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    g_err.clear();
+    if (!out) {
+        set_err("null result");
+        return GB_EINVAL;
+    }
+    return verify_u128(c, to_u128(A_lo, A_hi), to_u128(B_lo, B_hi), P_max, (hipStream_t)stream, out);
+}
+
+gb_status gb_is_prime_u128(const uint64_t *q, uint64_t count, uint8_t *is_prime, void *stream)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    g_err.clear();
+    if (count && (!q || !is_prime)) {
+        set_err("null device pointer");
+        return GB_EINVAL;
+    }
+    if (c.device >= 0)
+        GB_HIP(hipSetDevice(c.device));
+    GB_HIP(gb_launch_bpsw((const u128w *)q, count, is_prime, (hipStream_t)stream));
+    GB_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return GB_OK;
 }
 
 gb_status gb_set_allocator(gb_alloc_fn alloc, gb_free_fn free_, void *user)
