@@ -18,8 +18,9 @@
  *  - Arguments are validated before any work is enqueued (Sec. 3.5, resource
  *    validation before launch).
  *  - `stream` is a hipStream_t (NULL = the default stream).  The calls below
- *    enqueue their kernels on that stream and wait for it before returning,
- *    so results are in the caller's host structures on return.
+ *    enqueue their kernels on that stream and, except for
+ *    gb_verify_range_async, wait for it before returning, so results are in
+ *    the caller's host structures on return.
  *  - All u64 bounds up to 2^64 - 1 are accepted; the arithmetic inside is
  *    guarded against wrap-around up to that ceiling (Sec. 3.4).
  *  - One device per process: the device current at gb_base_primes() holds the
@@ -146,6 +147,31 @@ gb_status gb_table_read(uint32_t *out, uint64_t first, uint64_t count);
  */
 gb_status gb_verify_range(uint64_t A, uint64_t B, uint64_t P_max, void *stream,
                           gb_result *out);
+
+/*
+ * Stream-ordered form of gb_verify_range (Sec. 3.1: device-resident work
+ * structures, one asynchronous copy of the result at the end).  The whole
+ * launch sequence is enqueued on `stream` after the device work of the
+ * library's previous call, and ends with copies of the result record into
+ * *out, of the status into *status and of the unresolved list into
+ * out->unresolved; the call returns once everything is enqueued.  The caller
+ * synchronizes `stream` (or an event after it) before reading *out or
+ * *status.
+ *   out, status, out->unresolved   pinned host memory (hipHostMalloc or
+ *          registered); GB_EINVAL otherwise, before anything is enqueued.
+ *          out->unresolved / out->unresolved_cap are read at the call.
+ *   *status (written by the stream): GB_OK; GB_ETRUNC when the unresolved
+ *          list did not fit (counts exact); GB_ENOMEM when more evens were
+ *          left open by the probe window than the library's current spill
+ *          list holds: *out is then not valid, and the blocking
+ *          gb_verify_range (which grows the list) gives the result.
+ * Errors returned by the call itself as gb_verify_range (nothing enqueued).
+ * The host waits only when a workspace must grow, or when strike-bitmap
+ * descriptors still being uploaded by the previous call would be
+ * overwritten.  gb_last_stats() is not updated.
+ */
+gb_status gb_verify_range_async(uint64_t A, uint64_t B, uint64_t P_max, void *stream,
+                                gb_result *out, int32_t *status);
 
 /*
  * Verify k ranges in one persistent launch (batched form): workgroups claim

@@ -98,6 +98,7 @@ def lib():
         "gb_verify_range": (st, [u64, u64, u64, vp, ctypes.POINTER(Result)]),
         "gb_verify_batch": (st, [vp, u64, u64, vp, vp]),
         "gb_verify_range_noalloc": (st, [u64, u64, u64, vp, ctypes.POINTER(Result)]),
+        "gb_verify_range_async": (st, [u64, u64, u64, vp, vp, vp]),
         "gb_verify_range_u128": (st, [u64, u64, u64, u64, u64, vp, ctypes.POINTER(Result128)]),
         "gb_is_prime_u128": (st, [vp, u64, vp, vp]),
         "gb_set_allocator": (st, [ALLOC_FN, FREE_FN, vp]),
@@ -239,6 +240,37 @@ def is_prime_u128(values):
     _check(lib().gb_is_prime_u128(q.data_ptr(), len(values), out.data_ptr(),
                                   torch.cuda.current_stream().cuda_stream))
     return [bool(x) for x in out.cpu().tolist()]
+
+
+class AsyncVerify:
+    """gb_verify_range_async with its pinned buffers (PyTorch pinned host
+    tensors): launch() enqueues on a stream and returns at once; result()
+    reads the record after the caller has synchronized that stream."""
+
+    def __init__(self, unresolved_cap=1 << 12):
+        import torch
+        self.cap = int(unresolved_cap)
+        self._rec = torch.zeros(ctypes.sizeof(Result), dtype=torch.uint8, pin_memory=True)
+        self._status = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+        self._unres = torch.zeros(max(self.cap, 1), dtype=torch.int64, pin_memory=True)
+        self.rec = Result.from_address(self._rec.data_ptr())
+
+    def launch(self, A, B, P_max, stream=None):
+        self.rec.unresolved = ctypes.cast(self._unres.data_ptr(), ctypes.POINTER(ctypes.c_uint64))
+        self.rec.unresolved_cap = self.cap
+        self._status[0] = -1
+        _check(lib().gb_verify_range_async(int(A), int(B), int(P_max), _stream(stream),
+                                           ctypes.addressof(self.rec), self._status.data_ptr()))
+
+    def status(self):
+        return STATUS.get(int(self._status[0]), int(self._status[0]))
+
+    def result(self):
+        d = {f: int(getattr(self.rec, f)) for f in RESULT_FIELDS}
+        take = min(d["n_unresolved"], self.cap)
+        d["unresolved"] = [int(x) & M64 for x in self._unres[:take].tolist()]
+        d["status"] = self.status()
+        return d
 
 
 def verify_batch(intervals, P_max, stream=None, unresolved_cap=1024, allow_trunc=True):

@@ -239,4 +239,10 @@ hipError_t gb_launch_reduce(const GbInterval *iv, uint32_t k, const GbSegRecord 
                             uint64_t P_max, GbIvResult *res, hipStream_t s);
 hipError_t gb_launch_unres_emit(const GbSpill *spill, uint64_t spill_cap, const GbCounters *ctr,
                                 uint64_t P_max, uint64_t *out, uint32_t grid, hipStream_t s);
+// gb_result image and status word written by the finalize kernel (the status
+// at this byte offset of the image buffer).
+constexpr size_t kFinalizeStatusOffset = 96;
+hipError_t gb_launch_finalize(const GbIvResult *res, const GbCounters *ctr, uint64_t spill_cap,
+                              uint64_t A, uint64_t B, uint64_t P_max, uint64_t *unres,
+                              uint64_t cap, void *img, hipStream_t s);
 hipError_t gb_launch_is_prime(const uint64_t *q, uint64_t count, uint8_t *out, hipStream_t s);

@@ -17,6 +17,7 @@
 // depend on which workgroup claimed which segment.
 #include "gb_arith.h"
 #include "gb_internal.h"
+#include "goldbach.h"
 
 namespace {
 
@@ -181,7 +182,43 @@ __global__ __launch_bounds__(256) void is_prime_kernel(const uint64_t *q, uint64
         out[i] = gb_is_prime_u64(q[i]) ? 1 : 0;
 }
 
+// The stream-ordered end of gb_verify_range_async: the caller's gb_result
+// image and status word, built on the device from the reduced result and the
+// launch counters, for one copy to the caller's pinned memory.
+__global__ void finalize_kernel(const GbIvResult *res, const GbCounters *ctr, uint64_t spill_cap,
+                                uint64_t A, uint64_t B, uint64_t P_max, uint64_t *unres,
+                                uint64_t cap, gb_result *img, int32_t *status)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    const GbIvResult r = *res;
+    gb_result o;
+    o.A = A;
+    o.B = B;
+    o.P_max = P_max;
+    o.verified = r.verified;
+    o.max_p = r.max_p;
+    o.max_p_n = r.max_p_n;
+    o.checksum = r.checksum;
+    o.n_unresolved = r.n_unresolved;
+    o.n_failed = r.n_failed;
+    o.unresolved = unres;
+    o.unresolved_cap = cap;
+    *img = o;
+    *status = ctr->spills > spill_cap ? GB_ENOMEM : (r.n_unresolved > cap ? GB_ETRUNC : GB_OK);
+}
+
 }  // namespace
+
+hipError_t gb_launch_finalize(const GbIvResult *res, const GbCounters *ctr, uint64_t spill_cap,
+                              uint64_t A, uint64_t B, uint64_t P_max, uint64_t *unres,
+                              uint64_t cap, void *img, hipStream_t s)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, res, ctr, spill_cap, A, B, P_max,
+                       unres, cap, (gb_result *)img,
+                       (int32_t *)((char *)img + kFinalizeStatusOffset));
+    return hipGetLastError();
+}
 
 hipError_t gb_launch_phase2(const uint32_t *primes, uint64_t nprimes, uint64_t first_idx,
                             GbSpill *spill, uint64_t spill_cap, const GbCounters *ctr,

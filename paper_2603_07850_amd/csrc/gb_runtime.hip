@@ -181,6 +181,11 @@ struct Ctx {
     // workspaces of the verification past 2^64
     DevBuf d_wrec, d_wspill, d_wres, d_wunres, d_wctr;
     HostBuf h_wres;
+    // stream-ordered calls: the gb_result image they copy out, and the event
+    // that ends the last one's use of the shared workspaces
+    DevBuf d_async;
+    hipEvent_t ev_busy = nullptr;
+    bool async_pending = false;
 };
 
 Ctx &ctx()
@@ -233,6 +238,16 @@ gb_status use_device(Ctx &c)
     return GB_OK;
 }
 
+// Wait on the host until the last stream-ordered call no longer uses the
+// shared workspaces (before they are resized or released, or before a
+// blocking call enqueues work that reuses them).
+void quiesce(Ctx &c)
+{
+    if (c.async_pending && c.ev_busy)
+        (void)hipEventSynchronize(c.ev_busy);
+    c.async_pending = false;
+}
+
 bool params_valid(const gb_params &p)
 {
     if (!gb_probe_supported((int)p.seg_log2, (int)p.wg_size))
@@ -250,6 +265,11 @@ void release_all(Ctx &c)
     // once: nothing of the library may still be running on it
     if (c.device >= 0 && c.primes.p)
         (void)hipDeviceSynchronize();
+    c.async_pending = false;
+    if (c.ev_busy)
+        (void)hipEventDestroy(c.ev_busy);
+    c.ev_busy = nullptr;
+    c.d_async.release();
     c.primes.release();
     c.d_ctab.release();
     c.d_ptab.release();
@@ -1018,6 +1038,7 @@ gb_status verify_many(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, hi
         return GB_EINVAL;
     }
     GB_TRY(use_device(c));
+    quiesce(c);
     const gb_params pr = c.params;
     if (c.spill_cap == 0)
         c.spill_cap = 1 << 16;
@@ -1077,6 +1098,8 @@ gb_status verify_noalloc(Ctx &c, uint64_t A, uint64_t B, uint64_t P_max, hipStre
                          gb_result *out)
 {
     GB_TRY(use_device(c));
+    if (c.async_pending && c.ev_busy)   // order after a stream-ordered call, without waiting
+        GB_HIP(hipStreamWaitEvent(s, c.ev_busy, 0));
     char *base = (char *)g_scratch[c.device];
     if (!base) {
         set_err("the no-alloc scratch of device %d was not set up", c.device);
@@ -1164,6 +1187,93 @@ gb_status verify_noalloc(Ctx &c, uint64_t A, uint64_t B, uint64_t P_max, hipStre
             return GB_ETRUNC;
         }
     }
+    return GB_OK;
+}
+
+// Host memory the device copies can reach without staging (hipHostMalloc or
+// registered memory).
+bool is_pinned(const void *p)
+{
+    hipPointerAttribute_t at;
+    const hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeHost;
+}
+
+// gb_verify_range_async: the launch sequence of gb_verify_range, enqueued on
+// the caller's stream after the last call's use of the workspaces, ending in
+// copies of the result image, the status word and the unresolved list to the
+// caller's pinned memory.  Nothing waits on the host unless a workspace must
+// grow (or staging for strike-bitmap descriptors is in use by the last call).
+gb_status verify_async(Ctx &c, uint64_t A, uint64_t B, uint64_t P_max, hipStream_t s,
+                       gb_result *out, int32_t *status)
+{
+    GB_TRY(use_device(c));
+    const uint64_t cap = out->unresolved ? out->unresolved_cap : 0;
+    if (!is_pinned(out) || !is_pinned(status) || (cap && !is_pinned(out->unresolved))) {
+        set_err("gb_verify_range_async needs pinned host memory for out, status and "
+                "out->unresolved (hipHostMalloc)");
+        return GB_EINVAL;
+    }
+    const gb_params pr = c.params;
+    if (c.spill_cap == 0)
+        c.spill_cap = 1 << 16;
+    Plan pl;
+    const uint64_t AB[2] = {A, B};
+    GB_TRY(make_plan(c, AB, 1, P_max, pr, pl));
+    const size_t need_rec = std::max<uint64_t>(pl.total_segs, 1) * sizeof(GbSegRecord);
+    const size_t need_bm = std::max<uint64_t>(pl.max_bitmap_words, 1) * 4;
+    const size_t need_chunk = std::max<size_t>(pl.chunks.size(), 1) * sizeof(GbChunk);
+    const size_t need_task = std::max<size_t>(pl.tasks.size(), 1) * sizeof(GbFillTask);
+    const bool grows = need_rec > c.d_rec.bytes || need_bm > c.d_bitmap.bytes ||
+                       need_chunk > c.d_chunk.bytes || need_task > c.d_task.bytes ||
+                       !c.d_iv.p || !c.d_spill.p || !c.d_async.p;
+    if (grows || !pl.chunks.empty())
+        quiesce(c);
+    GB_TRY(c.d_iv.reserve(sizeof(GbInterval)));
+    GB_TRY(c.d_rec.reserve(need_rec));
+    GB_TRY(c.d_res.reserve(sizeof(GbIvResult)));
+    GB_TRY(c.d_ctr.reserve(sizeof(GbCounters)));
+    GB_TRY(c.d_done.reserve(sizeof(GbIvDone)));
+    GB_TRY(c.d_claims.reserve(std::max<size_t>(pl.rounds.size(), 1) * 8));
+    GB_TRY(c.d_chunk.reserve(need_chunk));
+    GB_TRY(c.h_chunk.reserve(need_chunk));
+    GB_TRY(c.d_task.reserve(need_task));
+    GB_TRY(c.h_task.reserve(need_task));
+    GB_TRY(c.d_bitmap.reserve(need_bm));
+    GB_TRY(c.d_spill.reserve(c.spill_cap * sizeof(GbSpill)));
+    GB_TRY(c.d_unres.reserve(c.spill_cap * sizeof(uint64_t)));
+    GB_TRY(c.d_async.reserve(128));
+    if (!c.ev_busy)
+        GB_HIP(hipEventCreateWithFlags(&c.ev_busy, hipEventDisableTiming));
+    uint32_t grid = 0;
+    GB_TRY(probe_grid(c, pl, pr, &grid));
+    if (c.async_pending)
+        GB_HIP(hipStreamWaitEvent(s, c.ev_busy, 0));
+    GB_HIP(gb_launch_put_interval((GbInterval *)c.d_iv.p, pl.dev_iv[0], s));
+    if (!pl.chunks.empty()) {
+        std::memcpy(c.h_chunk.p, pl.chunks.data(), pl.chunks.size() * sizeof(GbChunk));
+        GB_HIP(hipMemcpyAsync(c.d_chunk.p, c.h_chunk.p, pl.chunks.size() * sizeof(GbChunk),
+                              hipMemcpyHostToDevice, s));
+        std::memcpy(c.h_task.p, pl.tasks.data(), pl.tasks.size() * sizeof(GbFillTask));
+        GB_HIP(hipMemcpyAsync(c.d_task.p, c.h_task.p, pl.tasks.size() * sizeof(GbFillTask),
+                              hipMemcpyHostToDevice, s));
+    }
+    GB_TRY(enqueue_kernels(c, pl, P_max, pr, grid, s, false, library_ws(c)));
+    GB_HIP(gb_launch_finalize((const GbIvResult *)c.d_res.p, (const GbCounters *)c.d_ctr.p,
+                              c.spill_cap, pl.An[0], pl.Bn[0], P_max, out->unresolved,
+                              out->unresolved_cap, c.d_async.p, s));
+    GB_HIP(hipMemcpyAsync(out, c.d_async.p, sizeof(gb_result), hipMemcpyDeviceToHost, s));
+    GB_HIP(hipMemcpyAsync(status, (const char *)c.d_async.p + kFinalizeStatusOffset, 4,
+                          hipMemcpyDeviceToHost, s));
+    const uint64_t take = std::min<uint64_t>(cap, c.spill_cap);
+    if (take)
+        GB_HIP(hipMemcpyAsync(out->unresolved, c.d_unres.p, take * 8, hipMemcpyDeviceToHost, s));
+    GB_HIP(hipEventRecord(c.ev_busy, s));
+    c.async_pending = true;
     return GB_OK;
 }
 
@@ -1284,6 +1394,7 @@ gb_status verify_wide_part(Ctx &c, u128h A, u128h B, uint64_t P_max, hipStream_t
 gb_status verify_u128(Ctx &c, u128h A, u128h B, uint64_t P_max, hipStream_t s, gb_result128 *out)
 {
     GB_TRY(use_device(c));
+    quiesce(c);
     if (P_max < 2) {
         set_err("P_max must be >= 2 (got %llu)", (unsigned long long)P_max);
         return GB_EINVAL;
@@ -1454,6 +1565,19 @@ gb_status gb_verify_range_noalloc(uint64_t A, uint64_t B, uint64_t P_max, void *
         return GB_EINVAL;
     }
     return verify_noalloc(c, A, B, P_max, (hipStream_t)stream, out);
+}
+
+gb_status gb_verify_range_async(uint64_t A, uint64_t B, uint64_t P_max, void *stream,
+                                gb_result *out, int32_t *status)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    g_err.clear();
+    if (!out || !status) {
+        set_err("null result or status");
+        return GB_EINVAL;
+    }
+    return verify_async(c, A, B, P_max, (hipStream_t)stream, out, status);
 }
 
 gb_status gb_verify_range_u128(uint64_t A_lo, uint64_t A_hi, uint64_t B_lo, uint64_t B_hi,
