@@ -44,6 +44,14 @@ def log(msg):
     print("[gpu-scale] " + msg, flush=True)
 
 
+def golden(name):
+    """Oracle aggregates written by tests/golden/make_full_ranges.py."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        return json.load(f)
+
+
 def evens(A, B):
     return (B - A) // 2 + 1
 
@@ -99,10 +107,10 @@ SHAPES_C1 = [dict(seg_log2=18, wg_size=256, window=4096, bucket_log2=0),
 
 
 def test_c1_full_range_and_windows(gb, O):
-    """Every even n in [4, 10^10], base primes up to 10^5, P_max = 2^16: the
-    first 10^9 against the oracle in full, the 64 seeded 10^7-wide windows of
-    (10^9, 10^10] against the oracle, and the full range checked by counts and
-    by the merge of a split, at the three segment sizes."""
+    """Every even n in [4, 10^10], base primes up to 10^5, P_max = 2^16, at the
+    three segment sizes: the whole range against the oracle's aggregates of it
+    (tests/golden/full_1e10.json), the first 10^9 and the 64 seeded 10^7-wide
+    windows of (10^9, 10^10] against the oracle live, and the merge of a split."""
     gb.base_primes(100000)
     o1 = oracle_first_1e9(O)
     wins = W.gpu_scale_windows()
@@ -115,8 +123,8 @@ def test_c1_full_range_and_windows(gb, O):
         for (a, b), o, g in zip(wins, ow, gb.verify_batch(wins, 65536)):
             same(g, o, what="window %d %s" % (a, shape))
         f = gb.verify_range(4, 10**10, 65536)
-        assert f["verified"] == evens(4, 10**10)
-        assert f["n_unresolved"] == 0 and f["n_failed"] == 0
+        same(f, golden("full_1e10.json")["result"], FIELDS, "[4,1e10] against the oracle's "
+             "full-range aggregates %s" % shape)
         assert f["max_p"] >= max(o["max_p"] for o in ow + [o1])
         if full is None:
             full = f
@@ -132,10 +140,12 @@ def test_c1_full_range_and_windows(gb, O):
 
 def test_c2_headline_range(gb, O):
     """Every even n in [4, 10^12], base primes up to 10^6, P_max = 2^16, in the
-    benchmark's launch configurations: the first 10^9 and the 256 seeded
-    10^7-wide windows against the oracle, the full range by counts, by a
-    three-way split, and across launch configurations."""
+    benchmark's launch configurations: the whole range and its 100 slices of
+    5e9 evens against the oracle's aggregates (tests/golden/full_1e12.json),
+    the first 10^9 and the 256 seeded 10^7-wide windows against the oracle
+    live, a three-way split, and identity across launch configurations."""
     gb.base_primes(10**6)
+    g12 = golden("full_1e12.json")
     wins = W.headline_windows()
     ow = oracle_many(O, [(a, b, 65536, 10**6, 1 << 16) for a, b in wins])
     o1 = oracle_first_1e9(O)
@@ -152,8 +162,8 @@ def test_c2_headline_range(gb, O):
         t = time.time()
         f = gb.verify_range(4, 10**12, 65536)
         log("c2 full range %.3f s: %s" % (time.time() - t, {k: f[k] for k in AGG}))
-        assert f["verified"] == evens(4, 10**12)
-        assert f["n_unresolved"] == 0 and f["n_failed"] == 0
+        same(f, g12["result"], FIELDS, "[4,1e12] against the oracle's full-range aggregates %s"
+             % cfg)
         assert f["max_p"] >= max(o["max_p"] for o in ow + [o1])
         if full is None:
             full = f
@@ -163,33 +173,59 @@ def test_c2_headline_range(gb, O):
             parts = [gb.verify_range(4, c1, 65536), gb.verify_range(c1 + 2, c2, 65536),
                      gb.verify_range(c2 + 2, 10**12, 65536)]
             same(merge_gpu(O, parts), f, AGG, "split of [4,1e12] at %d, %d" % (c1, c2))
+            # the oracle's 100 slices of 5e9 evens, in one batched launch
+            sl = g12["slices"]
+            for o, g in zip(sl, gb.verify_batch([(x["A"], x["B"]) for x in sl], 65536)):
+                same(g, o, FIELDS, "slice [%d, %d]" % (o["A"], o["B"]))
         else:
             same(f, full, FIELDS, "[4,1e12] %s" % cfg)
+
+
+def golden_batch():
+    """Per-interval oracle results of the 4096-interval batch
+    (tests/golden/batch_4096.txt, written by make_full_ranges.py)."""
+    import os
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "batch_4096.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [int(x) for x in line.split()]
+            rows.append(dict(zip(("i", "A", "B", "verified", "checksum", "max_p", "max_p_n",
+                                  "n_unresolved", "n_failed"), v)))
+    return rows
 
 
 def test_c3_batch(gb, O):
     """The seeded batch of 4096 uneven intervals (16 ending next to 2^64 - 2),
     base primes up to 2^32, in one batched launch with the automatic
-    strike-bitmap policy: every interval fully verified with its maximum inside
-    it, and a seeded sample of the intervals short enough for the oracle
-    (at most 2^21 evens, all edge intervals among them) bit-exact."""
+    strike-bitmap policy: every interval bit-exact against the oracle's result
+    for it (tests/golden/batch_4096.txt), the 16 edge intervals among them;
+    and a seeded sample of the short intervals run through the oracle live,
+    which pins the fixture to the oracle as it stands."""
     T = 2**32 - 1
     gb.base_primes(T)
     gb.set_params(seg_log2=18, wg_size=512, window=4096, bucket_log2=0)
     ivs = W.batch_intervals()
+    want = golden_batch()
+    assert len(want) == len(ivs) == 4096
     t = time.time()
     got = gb.verify_batch(ivs, 65536)
     log("c3 batch %.3f s" % (time.time() - t))
-    for (a, b), g in zip(ivs, got):
-        assert g["A"] == a and g["B"] == b
-        assert g["verified"] == evens(a, b), (a, b)
-        assert g["n_unresolved"] == 0 and g["n_failed"] == 0, (a, b)
-        assert a <= g["max_p_n"] <= b and 2 <= g["max_p"] <= 65536, (a, b)
-    short = [i for i, (a, b) in enumerate(ivs) if evens(a, b) <= 1 << 21]
-    edge = [i for i in short if i >= len(ivs) - 16]
-    rest = sorted(set(short) - set(edge))
-    pick = edge + random.Random(11).sample(rest, 24)
-    log("c3 oracle sample: %d intervals (%d at the top of the range)" % (len(pick), len(edge)))
+    for (a, b), g, o in zip(ivs, got, want):
+        assert (o["A"], o["B"]) == (a, b) == (g["A"], g["B"])
+        for f in AGG:
+            assert g[f] == o[f], ("interval", o["i"], a, b, f, g[f], o[f])
+        assert g["unresolved"] == []
+    edge = list(range(len(ivs) - 16, len(ivs)))
+    assert all(ivs[i][1] >= (1 << 64) - 2 - 2 * 10**6 for i in edge)
+    # a second launch configuration gives the same results
+    gb.set_params(seg_log2=20, wg_size=1024, window=16384, bucket_log2=23)
+    got2 = gb.verify_batch(ivs, 65536)
+    assert got2 == got
+    short = [i for i, (a, b) in enumerate(ivs) if evens(a, b) <= 1 << 20]
+    pick = random.Random(11).sample(short, 16)
+    log("c3 live oracle sample: %d intervals" % len(pick))
     O.primes(T)   # build the oracle's table once, before the threads share it
     ow = oracle_many(O, [(ivs[i][0], ivs[i][1], 65536, T, 1 << 22) for i in pick])
     for i, o in zip(pick, ow):

@@ -62,6 +62,49 @@ def test_served_equals_alone(gb):
     assert st["completed"] == len(reqs) and st["ticks"] >= 2
 
 
+def test_served_large_requests_equal_alone(gb):
+    """The trace's large requests (L = 10^9 and 10^10 evens, starts near
+    1.8e19, where every piece takes one remainder per large prime) served in a
+    mix with small ones and with the server's default piece size: each result
+    bit-identical to the request verified alone, and seeded 10^7-wide windows
+    of the large requests against the oracle."""
+    from oracle import oracle as O
+    big = [(18 * 10**18 + 2 * 123456789, 18 * 10**18 + 2 * 123456789 + 2 * (10**9 - 1)),
+           (17 * 10**18, 17 * 10**18 + 2 * (10**9 - 1)),
+           (U64 - 1 - 2 * (10**10 - 1) - 2 * 777, U64 - 1 - 2 * 777)]
+    reqs = big + _mix(5, 20)
+    print("[gpu] served: %d requests, %d of them with 1e9+ evens" % (len(reqs), len(big)), flush=True)
+    alone = [gb.verify_range(a, b, 65536) for a, b in reqs]
+    with gb.Server(65536, max_active=16, piece_segments=256) as srv:
+        ids = {}
+        for i, (a, b) in enumerate(reqs):
+            ids[srv.submit(a, b)] = i
+        got = {}
+        while len(got) < len(reqs):
+            r = srv.poll(wait_ms=60000)
+            assert r is not None, "server stalled"
+            got[ids[r[0]]] = r[1]
+    for i in range(len(reqs)):
+        for f in FIELDS:
+            assert got[i][f] == alone[i][f], (f, reqs[i])
+    for a, b in big:
+        assert alone[big.index((a, b))]["verified"] == (b - a) // 2 + 1
+    import concurrent.futures as cf
+    rng = random.Random(9)
+    wins = []
+    for a, b in big:
+        s = a + 2 * rng.randrange(0, (b - a) // 2 - 10**7)
+        wins.append((s, s + 2 * (5 * 10**6 - 1)))
+    O.primes(2**32 - 1)
+    with cf.ThreadPoolExecutor(len(wins)) as ex:
+        ow = list(ex.map(lambda w: O.verify_range(w[0], w[1], 65536, 2**32 - 1,
+                                                  seg_evens=1 << 23), wins))
+    for w, o in zip(wins, ow):
+        g = gb.verify_range(*w, 65536)
+        for f in FIELDS:
+            assert g[f] == o[f], (f, w)
+
+
 def test_served_small_against_oracle(gb):
     from oracle import oracle as O
     reqs = [(4, 200000), (10**9, 10**9 + 123456), (U64 - 50000, U64), (10**15, 10**15 + 77776)]
