@@ -162,9 +162,10 @@ gb_status gb_verify_range(uint64_t A, uint64_t B, uint64_t P_max, void *stream,
  *          out->unresolved / out->unresolved_cap are read at the call.
  *   *status (written by the stream): GB_OK; GB_ETRUNC when the unresolved
  *          list did not fit (counts exact); GB_ENOMEM when more evens were
- *          left open by the probe window than the library's current spill
- *          list holds: *out is then not valid, and the blocking
- *          gb_verify_range (which grows the list) gives the result.
+ *          left open by the probe window than the spill list of this form
+ *          holds (the library's current list, at most 65536 entries): *out
+ *          is then not valid, and the blocking gb_verify_range (which grows
+ *          the list) gives the result.
  * Errors returned by the call itself as gb_verify_range (nothing enqueued).
  * The host waits only when a workspace must grow, or when strike-bitmap
  * descriptors still being uploaded by the previous call would be
@@ -175,10 +176,13 @@ gb_status gb_verify_range_async(uint64_t A, uint64_t B, uint64_t P_max, void *st
 
 /*
  * Verify k ranges in one persistent launch (batched form): workgroups claim
- * segments of all k ranges from one device queue with an atomic counter, and
- * the whole launch sequence is a captured HIP graph, re-instantiated only when
- * the batch's shape changes.  Results are identical to k separate
- * gb_verify_range() calls.
+ * segments of all k ranges from one device queue with an atomic counter (the
+ * device-side form of the work pool of Sec. 3.2, Alg. 1), and the whole
+ * launch sequence is a captured HIP graph (Sec. 5 names CUDA graphs as future
+ * work), re-instantiated only when the batch's shape changes.  Results are
+ * identical to k separate gb_verify_range() calls.  The workload it is built
+ * and measured for: thousands of uneven intervals per launch, lengths spread
+ * over 10^4..10^8 evens and starts over 10^9..2^64 - 2 (tables up to 2^32).
  *   AB     host array of 2k u64: A_0, B_0, A_1, B_1, ...
  *   outs   host array of k gb_result (unresolved buffers as in gb_verify_range).
  * Errors as gb_verify_range; GB_ETRUNC if any list was truncated.
@@ -249,9 +253,10 @@ gb_status gb_is_prime_u128(const uint64_t *q, uint64_t count, uint8_t *is_prime,
  *  - the range may span at most about 2.09 million segments of 2^seg_log2
  *    evens (5.5e11 evens at seg_log2 = 18, 2.2e12 at 20): longer ranges fail
  *    with GB_ENOMEM before anything is enqueued;
- *  - the evens left open by the probe window share what the segment records
- *    leave of the array; more than fit give GB_ENOMEM after the run (tiny
- *    P_max over long ranges), and the result is then not written;
+ *  - at most 65536 evens may be left open by the probe window (they share
+ *    what the segment records leave of the array); more give GB_ENOMEM
+ *    after the run (tiny P_max over long ranges), and the result is then not
+ *    written;
  *  - gb_last_stats() and gb_last_latencies() are not updated.
  * All calls on one device share its array and leave their contents in it.
  * Calls are serialized by the library lock and each waits for its stream
@@ -284,7 +289,11 @@ gb_status gb_get_params(gb_params *p);
  * segment size, workgroup size and probe window (and, when isqrt(B) > 2^22,
  * with and without strike bitmaps), keep the fastest as the current parameters
  * and write it to *best (may be NULL).  Results of later calls do not depend
- * on the choice.
+ * on the choice.  Built for full ranges [4, N] as in the paper's Table 1
+ * (N = 10^10 and 10^12 here): the calibration range is the top of the range.
+ * The choice is cached per device, range magnitude and P_max: a later call
+ * for the same key returns it without timing (gb_autotune_cache_clear()
+ * forgets every choice).
  */
 gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream,
                       gb_params *best);
@@ -297,9 +306,16 @@ gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream,
  * 2^(seg_log2+3), 2^(seg_log2+5)), keep the fastest as the current
  * parameters and write it to *best (may be NULL).  Results of later calls do
  * not depend on the choice.  GB_EINVAL for an empty or oversized sample.
+ * Built for the batched workload described at gb_verify_batch.  Cached like
+ * gb_autotune's choice, per device, sample (count, evens, largest top) and
+ * P_max.
  */
 gb_status gb_autotune_batch(const uint64_t *AB, uint64_t k, uint64_t P_max, void *stream,
                             gb_params *best);
+
+/* Forget every cached autotuner choice (the next gb_autotune /
+ * gb_autotune_batch times the candidates again). */
+gb_status gb_autotune_cache_clear(void);
 
 /*
  * Deterministic Miller-Rabin primality of `count` u64 values (Sec. 3.4: the
@@ -348,7 +364,10 @@ gb_status gb_last_stats(gb_stats *out);
 gb_status gb_last_latencies(double *ms, uint64_t k);
 
 /*
- * Served form: a request loop with continuous batching.  A server thread
+ * Served form (built for a Poisson stream of requests, 90 % of them 10^4..10^8
+ * evens, the rest 10^9 and 10^10 evens, starts up to 1.8e19, with a 64 GB
+ * admission budget; the work pool of Sec. 3.2 turned into a request loop): a
+ * request loop with continuous batching.  A server thread
  * admits submitted ranges while active slots and the HBM budget allow, and
  * runs ticks in which every active request contributes its next piece
  * (piece_segments segments) to one batched launch (gb_verify_batch); requests

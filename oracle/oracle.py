@@ -98,7 +98,8 @@ def table_limit(limit):
     return max(int(limit), 65536)
 
 
-def verify_range(A, B, P_max, limit, seg_evens=1 << 16, cap=1 << 16, want_pmin=False):
+def verify_range(A, B, P_max, limit, seg_evens=1 << 16, cap=1 << 16, want_pmin=False,
+                 unresolved_array=False):
     """Aggregates (and optionally per-n p_min) for every even n in [A, B].
 
     ``limit`` is the base-prime limit handed to gb_base_primes; the oracle
@@ -123,7 +124,8 @@ def verify_range(A, B, P_max, limit, seg_evens=1 << 16, cap=1 << 16, want_pmin=F
                                 pmin_ptr)
     out = {f: int(getattr(res, f)) for f, _ in OracleResult._fields_}
     out["status"] = int(st)
-    out["unresolved"] = [int(x) for x in unres[:min(out["n_unresolved"], cap)]]
+    k = min(out["n_unresolved"], cap)
+    out["unresolved"] = unres[:k].copy() if unresolved_array else [int(x) for x in unres[:k]]
     if want_pmin:
         out["pmin"] = pmin[: (out["B"] - out["A"]) // 2 + 1] if out["B"] >= out["A"] else pmin[:0]
     return out

@@ -106,6 +106,7 @@ def lib():
         "gb_get_params": (st, [ctypes.POINTER(Params)]),
         "gb_autotune": (st, [u64, u64, u64, vp, ctypes.POINTER(Params)]),
         "gb_autotune_batch": (st, [ctypes.POINTER(ctypes.c_uint64), u64, u64, vp, ctypes.POINTER(Params)]),
+        "gb_autotune_cache_clear": (st, []),
         "gb_is_prime_u64": (st, [vp, u64, vp, vp]),
         "gb_last_stats": (st, [ctypes.POINTER(Stats)]),
         "gb_debug_fail_next": (st, [ctypes.c_uint32]),
@@ -170,22 +171,28 @@ def table_read(first=0, count=None):
     return out[:count]
 
 
-def _to_dict(r, unres_buf):
+def _to_dict(r, unres_buf, as_array=False):
     d = {f: int(getattr(r, f)) for f in RESULT_FIELDS}
     take = min(d["n_unresolved"], int(r.unresolved_cap))
-    d["unresolved"] = [int(unres_buf[i]) for i in range(take)] if take else []
+    if as_array:
+        import numpy as np
+        d["unresolved"] = np.ctypeslib.as_array(unres_buf)[:take].copy()
+    else:
+        d["unresolved"] = [int(unres_buf[i]) for i in range(take)] if take else []
     return d
 
 
-def verify_range(A, B, P_max, stream=None, unresolved_cap=1 << 16, allow_trunc=True):
-    """Verify every even n in [A, B]; returns a dict of the gb_result fields."""
+def verify_range(A, B, P_max, stream=None, unresolved_cap=1 << 16, allow_trunc=True,
+                 unresolved_array=False):
+    """Verify every even n in [A, B]; returns a dict of the gb_result fields
+    (the unresolved list as a numpy array when unresolved_array)."""
     buf = (ctypes.c_uint64 * max(int(unresolved_cap), 1))()
     r = Result()
     r.unresolved = ctypes.cast(buf, ctypes.POINTER(ctypes.c_uint64))
     r.unresolved_cap = int(unresolved_cap)
     st = lib().gb_verify_range(int(A), int(B), int(P_max), _stream(stream), ctypes.byref(r))
     _check(st, ok=(0, 5) if allow_trunc else (0,))
-    d = _to_dict(r, buf)
+    d = _to_dict(r, buf, unresolved_array)
     d["status"] = STATUS[st]
     return d
 
@@ -323,6 +330,11 @@ def autotune_batch(intervals, P_max, stream=None):
     p = Params()
     _check(lib().gb_autotune_batch(AB, k, int(P_max), _stream(stream), ctypes.byref(p)))
     return p.as_dict()
+
+
+def autotune_cache_clear():
+    """Forget the library's cached autotuner choices."""
+    _check(lib().gb_autotune_cache_clear())
 
 
 def is_prime_u64(q):

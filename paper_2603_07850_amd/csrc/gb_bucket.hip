@@ -66,7 +66,6 @@ __device__ void fill_tile(const GbBucketArgs &a, uint64_t tile)
         const uint64_t idx = (uint64_t)p_first + pi;
         const uint32_t p = a.primes[idx];
         const double inv = gb_recip(p);
-        const uint64_t p2 = (uint64_t)p * p;
         const uint32_t pm3 = p % 3;
         for (uint32_t cc = 0; cc < c_n; ++cc) {
             const uint32_t ci = c_first + cc;
@@ -76,20 +75,31 @@ __device__ void fill_tile(const GbBucketArgs &a, uint64_t tile)
             const uint64_t dmax = chunk[ci].dmax;
             const uint64_t seg_first = chunk[ci].seg_first;
             const uint32_t nseg = chunk[ci].nseg;
-            // first odd multiple of p at or above max(Q0, p^2), as a window bit
-            const uint32_t r = gb_mod_u64_u32_inv(Q0, p, inv);
-            uint64_t x = r ? p - r : 0;
-            if (x & 1)
-                x += p;                                          // Q0 is odd: x must be even
-            uint64_t d = x >> 1;
-            if (p2 > Q0) {
-                const uint64_t dsq = (p2 - Q0) >> 1;
+            // Q0 mod p from one quotient estimate: Q0 / p < 2^41 here (p is a
+            // bucket prime, above 2^17), and the estimate from the rounded
+            // Q0 and the refined reciprocal is off by at most one, so the
+            // exact 64-bit residue Q0 - q p lies in (-p, 2p)
+            const double qd = __builtin_floor(chunk[ci].Q0d * inv);
+            const double qh = __builtin_floor(qd * (1.0 / 4294967296.0));
+            const uint32_t qhi = (uint32_t)qh;
+            const uint32_t qlo = (uint32_t)__builtin_fma(-qh, 4294967296.0, qd);
+            const uint64_t qp = (uint64_t)qlo * p + ((uint64_t)(qhi * p) << 32);
+            int64_t rr = (int64_t)(Q0 - qp);
+            rr += rr < 0 ? (int64_t)p : 0;
+            rr -= rr >= (int64_t)p ? (int64_t)p : 0;
+            const uint32_t r = (uint32_t)rr;
+            // first odd multiple of p at or above max(Q0, p^2), as a window
+            // bit: 2d = -Q0 (mod p)
+            const uint32_t x = r ? p - r : 0u;
+            uint64_t d = (x & 1) ? (x >> 1) + (p >> 1) + 1 : (x >> 1);
+            if (p > chunk[ci].sqrt_q0) {
+                const uint64_t dsq = ((uint64_t)p * p - Q0) >> 1;
                 if (dsq > d)
                     d = dsq;
             }
             // the odd number Q0 + 2d is a multiple of 3 when d = Q0 (mod 3):
             // the window does not store that class, so those bits are not struck
-            const uint32_t q0m3 = (uint32_t)(Q0 % 3);
+            const uint32_t q0m3 = chunk[ci].q0m3;
             uint32_t dm3 = (uint32_t)(d % 3);
             for (; d <= dmax; d += p) {
                 if (dm3 != q0m3) {

@@ -115,6 +115,9 @@ struct GbChunk {
     uint64_t dmax;        // last window bit any segment of the chunk reads
     uint32_t nseg;
     uint32_t p_root;      // one past the last table prime <= isqrt(Q0 + 2*dmax)
+    double Q0d;           // Q0 rounded to double (the quotient estimate's numerator)
+    uint32_t sqrt_q0;     // isqrt(Q0): only larger primes can have p^2 above Q0
+    uint32_t q0m3;        // Q0 mod 3
 };
 
 // One fill task: the table primes [p_first, p_first + np) of one band
@@ -206,12 +209,12 @@ void gb_internal_set_error(const char *msg);
 // Launch wrappers (each returns the hipError_t of its launch).
 hipError_t gb_launch_seed(uint32_t *seed, uint32_t *nseed, hipStream_t s);
 hipError_t gb_launch_table_count(const uint32_t *seed, const uint32_t *nseed, uint64_t T,
-                                 uint32_t nsegs, uint32_t *counts, hipStream_t s);
+                                 uint32_t nsegs, uint32_t *counts, uint32_t *stash, hipStream_t s);
 hipError_t gb_launch_table_scan(uint32_t *counts, uint32_t nsegs, uint64_t *total, hipStream_t s);
-hipError_t gb_launch_table_emit(const uint32_t *seed, const uint32_t *nseed, uint64_t T,
-                                uint32_t nsegs, const uint32_t *offsets, uint32_t *primes,
-                                hipStream_t s);
+hipError_t gb_launch_table_emit(const uint32_t *stash, uint32_t nsegs, const uint32_t *offsets,
+                                uint32_t *primes, hipStream_t s);
 uint32_t gb_table_seg_log2();
+uint32_t gb_table_block_words();   // 32-bit words of one block's stored bits
 
 hipError_t gb_launch_reset(GbCounters *ctr, GbIvDone *done, uint32_t k,
                            unsigned long long *claims, uint32_t nclaims, hipStream_t s);
@@ -245,4 +248,12 @@ constexpr size_t kFinalizeStatusOffset = 96;
 hipError_t gb_launch_finalize(const GbIvResult *res, const GbCounters *ctr, uint64_t spill_cap,
                               uint64_t A, uint64_t B, uint64_t P_max, uint64_t *unres,
                               uint64_t cap, void *img, hipStream_t s);
+// Unresolved list by bitmap and scan (one bit per even of each interval; the
+// bits of interval i start at word woff[i]), for lists too long for the
+// pairwise ranking.
+hipError_t gb_launch_unres_bitmap(const GbSpill *spill, uint64_t spill_cap, const GbCounters *ctr,
+                                  uint64_t P_max, const GbInterval *iv, uint32_t k,
+                                  const uint64_t *woff, uint64_t words, uint32_t *bitmap,
+                                  uint64_t *blocksum, uint64_t *out, uint32_t grid, hipStream_t s);
+uint64_t gb_unres_bitmap_blocks(uint64_t words);
 hipError_t gb_launch_is_prime(const uint64_t *q, uint64_t count, uint8_t *out, hipStream_t s);

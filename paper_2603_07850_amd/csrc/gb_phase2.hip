@@ -174,6 +174,131 @@ __global__ __launch_bounds__(256) void unres_emit_kernel(const GbSpill *spill, u
     }
 }
 
+// Unresolved n in (interval, n) order for long lists: one bit per even of
+// every interval (interval i's bits start at word woff[i]), set for each
+// unresolved spill; a scan of the words' popcounts gives each bit its
+// position.  Cost: linear in the evens of the launch and in the spills.
+constexpr uint32_t kEmitWordsPerBlock = 4096;   // 4 words per thread, 1024 threads
+
+__global__ __launch_bounds__(256) void emit_zero_kernel(uint32_t *bitmap, uint64_t words)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+        bitmap[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void emit_mark_kernel(const GbSpill *spill, uint64_t cap,
+                                                        const GbCounters *ctr, uint64_t P_max,
+                                                        const GbInterval *iv,
+                                                        const uint64_t *woff, uint32_t *bitmap)
+{
+    const unsigned long long total = ctr->spills;
+    const uint64_t count = total < cap ? total : cap;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride) {
+        const GbSpill sp = spill[e];
+        if (!unresolved(sp, P_max))
+            continue;
+        const uint64_t idx = (sp.n - iv[sp.iv].A) >> 1;   // the even's index in its interval
+        atomicOr(&bitmap[woff[sp.iv] + (idx >> 5)], 1u << (idx & 31));
+    }
+}
+
+// Per block of kEmitWordsPerBlock words: the number of set bits.
+__global__ __launch_bounds__(1024) void emit_count_kernel(const uint32_t *bitmap, uint64_t words,
+                                                         uint64_t *blocksum)
+{
+    __shared__ uint64_t sh[16];
+    const uint64_t w0 = (uint64_t)blockIdx.x * kEmitWordsPerBlock;
+    uint64_t c = 0;
+    for (uint32_t t = threadIdx.x; t < kEmitWordsPerBlock; t += 1024)
+        if (w0 + t < words)
+            c += __popc(bitmap[w0 + t]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t s = 0;
+        for (int i = 0; i < 16; ++i)
+            s += sh[i];
+        blocksum[blockIdx.x] = s;
+    }
+}
+
+// Exclusive scan of the block sums in place (one workgroup).
+__global__ __launch_bounds__(1024) void emit_scan_kernel(uint64_t *blocksum, uint64_t nblocks)
+{
+    __shared__ uint64_t sh[1024];
+    uint64_t run = 0;
+    for (uint64_t base = 0; base < nblocks; base += 1024) {
+        const uint64_t i = base + threadIdx.x;
+        const uint64_t v = i < nblocks ? blocksum[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (uint32_t off = 1; off < 1024; off <<= 1) {
+            const uint64_t y = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (i < nblocks)
+            blocksum[i] = run + sh[threadIdx.x] - v;
+        run += sh[1023];
+        __syncthreads();
+    }
+}
+
+// Emit: thread t of block b holds words 4t..4t+3 of the block; the position
+// of a bit is the block's offset + the set bits before it in the block.
+__global__ __launch_bounds__(1024) void emit_write_kernel(const uint32_t *bitmap, uint64_t words,
+                                                         const uint64_t *blockoff,
+                                                         const GbInterval *iv, uint32_t k,
+                                                         const uint64_t *woff, uint64_t *out)
+{
+    __shared__ uint64_t sh[1024];
+    const uint64_t w0 = (uint64_t)blockIdx.x * kEmitWordsPerBlock + 4ull * threadIdx.x;
+    uint32_t v[4];
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v[q] = w0 + q < words ? bitmap[w0 + q] : 0u;
+        c += __popc(v[q]);
+    }
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        const uint64_t y = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += y;
+        __syncthreads();
+    }
+    uint64_t pos = blockoff[blockIdx.x] + sh[threadIdx.x] - c;
+    if (c == 0)
+        return;
+    // the interval of word w0: last i with woff[i] <= w0
+    uint32_t lo = 0, hi = k - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (woff[mid] <= w0)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint64_t w = w0 + q;
+        while (lo + 1 < k && woff[lo + 1] <= w)
+            ++lo;
+        for (uint32_t m = v[q]; m; m &= m - 1) {
+            const uint64_t idx = (w - woff[lo]) * 32 + (uint32_t)(__ffs(m) - 1);
+            out[pos++] = iv[lo].A + 2 * idx;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void is_prime_kernel(const uint64_t *q, uint64_t count,
                                                        uint8_t *out)
 {
@@ -244,6 +369,30 @@ hipError_t gb_launch_unres_emit(const GbSpill *spill, uint64_t spill_cap, const 
     hipLaunchKernelGGL(unres_emit_kernel, dim3(grid), dim3(256), 0, s, spill, spill_cap, ctr,
                        P_max, out);
     return hipGetLastError();
+}
+
+hipError_t gb_launch_unres_bitmap(const GbSpill *spill, uint64_t spill_cap, const GbCounters *ctr,
+                                  uint64_t P_max, const GbInterval *iv, uint32_t k,
+                                  const uint64_t *woff, uint64_t words, uint32_t *bitmap,
+                                  uint64_t *blocksum, uint64_t *out, uint32_t grid, hipStream_t s)
+{
+    const uint64_t nb = (words + kEmitWordsPerBlock - 1) / kEmitWordsPerBlock;
+    if (nb == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(emit_zero_kernel, dim3(grid), dim3(256), 0, s, bitmap, words);
+    hipLaunchKernelGGL(emit_mark_kernel, dim3(grid), dim3(256), 0, s, spill, spill_cap, ctr, P_max,
+                       iv, woff, bitmap);
+    hipLaunchKernelGGL(emit_count_kernel, dim3((uint32_t)nb), dim3(1024), 0, s, bitmap, words,
+                       blocksum);
+    hipLaunchKernelGGL(emit_scan_kernel, dim3(1), dim3(1024), 0, s, blocksum, nb);
+    hipLaunchKernelGGL(emit_write_kernel, dim3((uint32_t)nb), dim3(1024), 0, s, bitmap, words,
+                       blocksum, iv, k, woff, out);
+    return hipGetLastError();
+}
+
+uint64_t gb_unres_bitmap_blocks(uint64_t words)
+{
+    return (words + kEmitWordsPerBlock - 1) / kEmitWordsPerBlock;
 }
 
 hipError_t gb_launch_is_prime(const uint64_t *q, uint64_t count, uint8_t *out, hipStream_t s)

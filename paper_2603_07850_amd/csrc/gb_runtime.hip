@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -177,6 +178,9 @@ struct Ctx {
     // strike bitmaps of the large primes, their chunks and fill tasks
     DevBuf d_bitmap, d_chunk, d_claims, d_task;
     HostBuf h_chunk, h_task;
+    // bitmap-and-scan emission of long unresolved lists
+    DevBuf d_woff, d_ubits, d_ublock;
+    HostBuf h_woff;
     std::vector<uint64_t> last_slot;    // last call: caller's index -> kernel slot
     // workspaces of the verification past 2^64
     DevBuf d_wrec, d_wspill, d_wres, d_wunres, d_wctr;
@@ -186,6 +190,8 @@ struct Ctx {
     DevBuf d_async;
     hipEvent_t ev_busy = nullptr;
     bool async_pending = false;
+    // autotuner choices by (device, kind, P_max, size class of the calibration)
+    std::map<std::vector<uint64_t>, gb_params> tuned;
 };
 
 Ctx &ctx()
@@ -285,6 +291,10 @@ void release_all(Ctx &c)
     c.d_chunk.release();
     c.d_claims.release();
     c.d_task.release();
+    c.d_woff.release();
+    c.d_ubits.release();
+    c.d_ublock.release();
+    c.h_woff.release();
     c.h_chunk.release();
     c.h_task.release();
     c.graph_key.clear();
@@ -349,7 +359,7 @@ gb_status build_table(Ctx &c, uint64_t limit)
     // pi(x) < 1.25506 x / ln x for x > 1 (Rosser and Schoenfeld 1962)
     const uint64_t cap = (uint64_t)(1.25506 * (double)T / std::log((double)T)) + 64;
 
-    DevBuf seed, counts;
+    DevBuf seed, counts, stash;
     gb_status st;
     if ((st = seed.reserve(8192 * 4 + 64)) != GB_OK)
         return st;
@@ -357,9 +367,17 @@ gb_status build_table(Ctx &c, uint64_t limit)
         seed.release();
         return st;
     }
+    // each table block's sieved bits, written by the count pass and read by
+    // the emit pass (T / 16 bytes: 256 MiB for T = 2^32 - 1)
+    if ((st = stash.reserve((size_t)nsegs * gb_table_block_words() * 4)) != GB_OK) {
+        seed.release();
+        counts.release();
+        return st;
+    }
     if ((st = c.primes.reserve(cap * 4)) != GB_OK) {
         seed.release();
         counts.release();
+        stash.release();
         return st;
     }
     uint32_t *d_seed = (uint32_t *)seed.p;
@@ -368,16 +386,18 @@ gb_status build_table(Ctx &c, uint64_t limit)
     hipStream_t s = nullptr;
     hipError_t e = gb_launch_seed(d_seed, d_nseed, s);
     if (e == hipSuccess)
-        e = gb_launch_table_count(d_seed, d_nseed, T, nsegs, (uint32_t *)counts.p, s);
+        e = gb_launch_table_count(d_seed, d_nseed, T, nsegs, (uint32_t *)counts.p,
+                                  (uint32_t *)stash.p, s);
     if (e == hipSuccess)
         e = gb_launch_table_scan((uint32_t *)counts.p, nsegs, d_total, s);
     if (e == hipSuccess)
-        e = gb_launch_table_emit(d_seed, d_nseed, T, nsegs, (uint32_t *)counts.p,
+        e = gb_launch_table_emit((const uint32_t *)stash.p, nsegs, (uint32_t *)counts.p,
                                  (uint32_t *)c.primes.p, s);
     uint64_t total = 0;
     if (e == hipSuccess)
         e = hipMemcpy(&total, d_total, 8, hipMemcpyDeviceToHost);
     seed.release();
+    stash.release();
     if (e != hipSuccess) {
         counts.release();
         set_err("prime table build failed: %s", hipGetErrorString(e));
@@ -509,6 +529,12 @@ uint64_t pi_upper(uint64_t x) { return (uint64_t)(1.25506 * (double)x / std::log
 // the small first round finishes the cheapest intervals of the batch early
 // (median completion 24 ms instead of 141 ms, at 0.192 s per launch).  Memory
 // is taken only for the segments a round holds.
+// Unresolved lists of up to kRankEmitMax entries are ordered by pairwise
+// ranking; longer ones by a bitmap of the evens and a scan, at most
+// kEmitBitmapMaxBytes of bitmap.
+constexpr uint64_t kRankEmitMax = 1ull << 16;
+constexpr uint64_t kEmitBitmapMaxBytes = 8ull << 30;
+
 constexpr uint32_t kBucketMibFirst = 512;
 constexpr uint32_t kBucketMibDefault = 8192;
 
@@ -692,6 +718,9 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
             ch.Q0 = n0 - 1 - 2ull * pl.H;                         // n0 > 2H + 2 here
             ch.dmax = (top - ch.Q0) / 2;
             ch.p_root = 0;                                        // set on the device
+            ch.Q0d = (double)ch.Q0;
+            ch.sqrt_q0 = (uint32_t)isqrt_u64(ch.Q0);
+            ch.q0m3 = (uint32_t)(ch.Q0 % 3);
             if (cur.nsegs && (cur.nsegs + ns) * (uint64_t)pl.words * 4 > round_budget) {
                 close_round();
                 if (auto_budget)
@@ -737,6 +766,12 @@ struct Ws {
     GbChunk *chunk = nullptr;
     GbFillTask *task = nullptr;
     uint32_t *bitmap = nullptr;
+    // long unresolved lists: one bit per even, interval i from word woff[i]
+    bool emit_by_bitmap = false;
+    uint64_t *woff = nullptr;
+    uint32_t *ubits = nullptr;
+    uint64_t *ublock = nullptr;
+    uint64_t ubits_words = 0;
 };
 
 Ws library_ws(const Ctx &c)
@@ -822,8 +857,13 @@ gb_status enqueue_kernels(Ctx &c, const Plan &pl, uint64_t P_max, const gb_param
     GB_HIP(gb_launch_phase2((const uint32_t *)c.primes.p, c.nprimes, (uint64_t)pl.ncand + 1,
                             w.spill, w.spill_cap, ctr, (uint32_t)c.num_cu * 4, s));
     GB_HIP(gb_launch_reduce(w.iv, (uint32_t)k, w.rec, w.spill, w.spill_cap, ctr, P_max, w.res, s));
-    GB_HIP(gb_launch_unres_emit(w.spill, w.spill_cap, ctr, P_max, w.unres,
-                                (uint32_t)c.num_cu * 2, s));
+    if (w.emit_by_bitmap)
+        GB_HIP(gb_launch_unres_bitmap(w.spill, w.spill_cap, ctr, P_max, w.iv, (uint32_t)k, w.woff,
+                                      w.ubits_words, w.ubits, w.ublock, w.unres,
+                                      (uint32_t)c.num_cu * 4, s));
+    else
+        GB_HIP(gb_launch_unres_emit(w.spill, w.spill_cap, ctr, P_max, w.unres,
+                                    (uint32_t)c.num_cu * 2, s));
     return GB_OK;
 }
 
@@ -862,7 +902,7 @@ std::vector<uint64_t> graph_key(const Ctx &c, const Plan &pl, uint64_t P_max, co
 // Capture the launch sequence on the library's own stream (the legacy default
 // stream cannot be captured) and instantiate it; reused while the key holds.
 gb_status capture_graph(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params &pr,
-                        uint32_t grid, const std::vector<uint64_t> &key)
+                        uint32_t grid, const std::vector<uint64_t> &key, const Ws &w)
 {
     if (c.graph_exec && c.graph_key == key)
         return GB_OK;
@@ -870,7 +910,7 @@ gb_status capture_graph(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params 
     if (!c.cap_stream)
         GB_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
     GB_HIP(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
-    gb_status st = enqueue_kernels(c, pl, P_max, pr, grid, c.cap_stream, false, library_ws(c));
+    gb_status st = enqueue_kernels(c, pl, P_max, pr, grid, c.cap_stream, false, w);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(c.cap_stream, &graph);
     if (st != GB_OK) {
@@ -943,6 +983,34 @@ gb_status run_once_impl(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params 
     GB_TRY(c.h_done.reserve(k * sizeof(GbIvDone)));
     GB_TRY(c.d_spill.reserve(c.spill_cap * sizeof(GbSpill)));
     GB_TRY(c.d_unres.reserve(c.spill_cap * sizeof(uint64_t)));
+    Ws w = library_ws(c);
+    // unresolved lists longer than the pairwise ranking handles: one bit per
+    // even of each interval, then a scan
+    std::vector<uint64_t> woff;
+    if (c.spill_cap > kRankEmitMax) {
+        woff.resize(k);
+        uint64_t words = 0;
+        for (uint64_t j = 0; j < k; ++j) {
+            woff[j] = words;
+            words += (pl.dev_iv[j].nE + 31) / 32;
+        }
+        if (words * 4 > kEmitBitmapMaxBytes) {
+            set_err("%llu evens were left open by P_max; listing them in order needs %llu MiB "
+                    "(at most %llu MiB): raise P_max or split the range",
+                    (unsigned long long)c.spill_cap, (unsigned long long)(words * 4 >> 20),
+                    (unsigned long long)(kEmitBitmapMaxBytes >> 20));
+            return GB_ENOMEM;
+        }
+        GB_TRY(c.d_woff.reserve(k * 8));
+        GB_TRY(c.h_woff.reserve(k * 8));
+        GB_TRY(c.d_ubits.reserve(std::max<uint64_t>(words, 1) * 4));
+        GB_TRY(c.d_ublock.reserve(std::max<uint64_t>(gb_unres_bitmap_blocks(words), 1) * 8));
+        w.emit_by_bitmap = true;
+        w.woff = (uint64_t *)c.d_woff.p;
+        w.ubits = (uint32_t *)c.d_ubits.p;
+        w.ublock = (uint64_t *)c.d_ublock.p;
+        w.ubits_words = words;
+    }
     for (auto &e : c.ev)
         if (!e)
             GB_HIP(hipEventCreate(&e));
@@ -952,6 +1020,10 @@ gb_status run_once_impl(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params 
     std::memcpy(c.h_iv.p, pl.dev_iv.data(), k * sizeof(GbInterval));
     enqueued = true;
     GB_HIP(hipMemcpyAsync(c.d_iv.p, c.h_iv.p, k * sizeof(GbInterval), hipMemcpyHostToDevice, s));
+    if (w.emit_by_bitmap) {
+        std::memcpy(c.h_woff.p, woff.data(), k * 8);
+        GB_HIP(hipMemcpyAsync(c.d_woff.p, c.h_woff.p, k * 8, hipMemcpyHostToDevice, s));
+    }
     if (!pl.chunks.empty()) {
         std::memcpy(c.h_chunk.p, pl.chunks.data(), pl.chunks.size() * sizeof(GbChunk));
         GB_HIP(hipMemcpyAsync(c.d_chunk.p, c.h_chunk.p, pl.chunks.size() * sizeof(GbChunk),
@@ -964,11 +1036,16 @@ gb_status run_once_impl(Ctx &c, const Plan &pl, uint64_t P_max, const gb_params 
     }
     GB_HIP(hipEventRecord(c.ev[0], s));
     if (use_graph) {
-        const std::vector<uint64_t> key = graph_key(c, pl, P_max, pr, grid);
-        GB_TRY(capture_graph(c, pl, P_max, pr, grid, key));
+        std::vector<uint64_t> key = graph_key(c, pl, P_max, pr, grid);
+        key.push_back(w.emit_by_bitmap);
+        key.push_back((uint64_t)w.woff);
+        key.push_back((uint64_t)w.ubits);
+        key.push_back((uint64_t)w.ublock);
+        key.push_back(w.ubits_words);
+        GB_TRY(capture_graph(c, pl, P_max, pr, grid, key, w));
         GB_HIP(hipGraphLaunch(c.graph_exec, s));
     } else {
-        GB_TRY(enqueue_kernels(c, pl, P_max, pr, grid, s, true, library_ws(c)));
+        GB_TRY(enqueue_kernels(c, pl, P_max, pr, grid, s, true, w));
     }
     if (inject == 2) {
         set_err("failure injected after the kernels were enqueued (test hook)");
@@ -1045,15 +1122,16 @@ gb_status verify_many(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, hi
     Plan pl;
     uint64_t spills = 0;
     GB_TRY(make_plan(c, AB, k, P_max, pr, pl));
-    for (int attempt = 0;; ++attempt) {
+    GB_TRY(run_once(c, pl, P_max, pr, s, use_graph, &spills));
+    if (spills > c.spill_cap) {
+        // the count is exact (every append counts, stored or not), so one
+        // rerun with room for all of them completes the call
+        c.spill_cap = spills + spills / 8 + 1024;
         GB_TRY(run_once(c, pl, P_max, pr, s, use_graph, &spills));
-        if (spills <= c.spill_cap)
-            break;
-        if (attempt >= 3) {
-            set_err("spill list kept overflowing (%llu entries)", (unsigned long long)spills);
+        if (spills > c.spill_cap) {
+            set_err("spill list overflowed twice (%llu entries)", (unsigned long long)spills);
             return GB_ENOMEM;
         }
-        c.spill_cap = spills + spills / 4 + 1024;   // rerun with room for every spill
     }
     const GbIvResult *res = (const GbIvResult *)c.h_res.p;
     c.last_slot = pl.slot;
@@ -1112,7 +1190,9 @@ gb_status verify_noalloc(Ctx &c, uint64_t A, uint64_t B, uint64_t P_max, hipStre
     GB_TRY(make_plan(c, AB, 1, P_max, pr, pl));
     const uint64_t rec_bytes = (pl.total_segs * sizeof(GbSegRecord) + 255) / 256 * 256;
     const uint64_t left = kScratchBytes - kScrRec >= rec_bytes ? kScratchBytes - kScrRec - rec_bytes : 0;
-    const uint64_t spill_cap = left / (sizeof(GbSpill) + sizeof(uint64_t));
+    // (lists are ordered by pairwise ranking here, so at most kRankEmitMax)
+    const uint64_t spill_cap =
+        std::min<uint64_t>(left / (sizeof(GbSpill) + sizeof(uint64_t)), kRankEmitMax);
     if (spill_cap < kScrMinSpill) {
         set_err("range of %llu segments needs %llu bytes of segment records; the no-alloc "
                 "scratch holds %llu bytes (at most %llu segments of 2^%u evens)",
@@ -1262,14 +1342,18 @@ gb_status verify_async(Ctx &c, uint64_t A, uint64_t B, uint64_t P_max, hipStream
         GB_HIP(hipMemcpyAsync(c.d_task.p, c.h_task.p, pl.tasks.size() * sizeof(GbFillTask),
                               hipMemcpyHostToDevice, s));
     }
-    GB_TRY(enqueue_kernels(c, pl, P_max, pr, grid, s, false, library_ws(c)));
+    // unresolved lists are ordered by pairwise ranking on this path, so the
+    // spill list used is at most kRankEmitMax entries long
+    Ws w = library_ws(c);
+    w.spill_cap = std::min<uint64_t>(c.spill_cap, kRankEmitMax);
+    GB_TRY(enqueue_kernels(c, pl, P_max, pr, grid, s, false, w));
     GB_HIP(gb_launch_finalize((const GbIvResult *)c.d_res.p, (const GbCounters *)c.d_ctr.p,
-                              c.spill_cap, pl.An[0], pl.Bn[0], P_max, out->unresolved,
+                              w.spill_cap, pl.An[0], pl.Bn[0], P_max, out->unresolved,
                               out->unresolved_cap, c.d_async.p, s));
     GB_HIP(hipMemcpyAsync(out, c.d_async.p, sizeof(gb_result), hipMemcpyDeviceToHost, s));
     GB_HIP(hipMemcpyAsync(status, (const char *)c.d_async.p + kFinalizeStatusOffset, 4,
                           hipMemcpyDeviceToHost, s));
-    const uint64_t take = std::min<uint64_t>(cap, c.spill_cap);
+    const uint64_t take = std::min<uint64_t>(cap, w.spill_cap);
     if (take)
         GB_HIP(hipMemcpyAsync(out->unresolved, c.d_unres.p, take * 8, hipMemcpyDeviceToHost, s));
     GB_HIP(hipEventRecord(c.ev_busy, s));
@@ -1704,6 +1788,21 @@ gb_status tune(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, hipStream
 
 }  // namespace
 
+// floor(log2(x)) for x >= 1 (0 for 0): the size classes of the tuner cache.
+uint64_t log2_floor(uint64_t x) { return x ? 63 - (uint64_t)__builtin_clzll(x) : 0; }
+
+// A cached choice for `key`, applied as the current parameters.
+bool tune_cached(Ctx &c, const std::vector<uint64_t> &key, gb_params *best)
+{
+    const auto it = c.tuned.find(key);
+    if (it == c.tuned.end())
+        return false;
+    c.params = it->second;
+    if (best)
+        *best = it->second;
+    return true;
+}
+
 gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream, gb_params *best)
 {
     Ctx &c = ctx();
@@ -1715,13 +1814,31 @@ gb_status gb_autotune(uint64_t A, uint64_t B, uint64_t P_max, void *stream, gb_p
         set_err("calibration range must be non-empty and hold at most 2^36 evens");
         return GB_EINVAL;
     }
+    const std::vector<uint64_t> key = {(uint64_t)c.device, 0, P_max, log2_floor(Bn),
+                                       log2_floor((Bn - An) / 2 + 1)};
+    if (tune_cached(c, key, best))
+        return GB_OK;
     // the bucket bound matters only when the range reaches primes above the
     // smallest automatic bound, 2^22
     std::vector<uint32_t> bounds = {c.params.bucket_log2};
     if (isqrt_u64(Bn) > (1ull << 22))
         bounds = {0, 32};
     const uint64_t AB[2] = {A, B};
-    return tune(c, AB, 1, P_max, (hipStream_t)stream, bounds, false, best);
+    gb_params chosen;
+    GB_TRY(tune(c, AB, 1, P_max, (hipStream_t)stream, bounds, false, &chosen));
+    c.tuned[key] = chosen;
+    if (best)
+        *best = chosen;
+    return GB_OK;
+}
+
+gb_status gb_autotune_cache_clear(void)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    g_err.clear();
+    c.tuned.clear();
+    return GB_OK;
 }
 
 gb_status gb_autotune_batch(const uint64_t *AB, uint64_t k, uint64_t P_max, void *stream,
@@ -1735,19 +1852,30 @@ gb_status gb_autotune_batch(const uint64_t *AB, uint64_t k, uint64_t P_max, void
         set_err("calibration batch must hold at least one interval");
         return GB_EINVAL;
     }
-    uint64_t evens = 0;
+    uint64_t evens = 0, top = 0;
     for (uint64_t i = 0; i < k; ++i) {
         uint64_t An, Bn;
-        if (normalize(AB[2 * i], AB[2 * i + 1], &An, &Bn))
+        if (normalize(AB[2 * i], AB[2 * i + 1], &An, &Bn)) {
             evens += (Bn - An) / 2 + 1;
+            top = std::max(top, Bn);
+        }
     }
     if (evens == 0 || evens > (1ull << 36)) {
         set_err("calibration batch must hold between 1 and 2^36 evens");
         return GB_EINVAL;
     }
+    const std::vector<uint64_t> key = {(uint64_t)c.device, 1, P_max, log2_floor(k),
+                                       log2_floor(evens), log2_floor(top)};
+    if (tune_cached(c, key, best))
+        return GB_OK;
     // automatic bound, and bounds 2^(seg_log2 + 3) and 2^(seg_log2 + 5)
     const std::vector<uint32_t> bounds = {0, 3, 5};
-    return tune(c, AB, k, P_max, (hipStream_t)stream, bounds, true, best);
+    gb_params chosen;
+    GB_TRY(tune(c, AB, k, P_max, (hipStream_t)stream, bounds, true, &chosen));
+    c.tuned[key] = chosen;
+    if (best)
+        *best = chosen;
+    return GB_OK;
 }
 
 gb_status gb_is_prime_u64(const uint64_t *q, uint64_t count, uint8_t *is_prime, void *stream)

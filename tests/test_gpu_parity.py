@@ -324,10 +324,17 @@ def test_range_autotuner_keeps_results(gb, O):
     table(gb, 10**6)
     saved = gb.get_params()
     try:
+        import time
+        gb.autotune_cache_clear()
         p = gb.autotune(10**11, 10**11 + 2 * 4_000_000, 65536)
         assert p["seg_log2"] in (18, 19, 20) and p["wg_size"] in (256, 512, 1024)
         assert gb.get_params() == p
         check(gb, O, 10**11, 10**11 + 2 * 4_000_000, 65536, 10**6)
+        # the choice is cached per device and size class: no timing again
+        gb.set_params(**saved)
+        t0 = time.perf_counter()
+        assert gb.autotune(10**11 + 2 * 10, 10**11 + 2 * 4_000_010, 65536) == p
+        assert time.perf_counter() - t0 < 0.05 and gb.get_params() == p
     finally:
         gb.set_params(**saved)
 
@@ -392,3 +399,37 @@ def test_max_ties_smallest_n(gb, shape):
                 assert g[f] == gbat[f] == w[f], (f, w["A"], g[f], gbat[f], w[f])
     finally:
         gb.set_params(**saved)
+
+
+def test_tiny_pmax_long_range(gb, O):
+    """P_max = 3 over 10^7 evens: about 8.5 million evens go to Phase 2, and the
+    ordered list is built by the bitmap-and-scan emission (the spill list
+    overflows once and the call reruns once with room for every spill).
+    Every field, the whole list included, equals the oracle's."""
+    import concurrent.futures as cf
+    import numpy as np
+    table(gb, 10**6)
+    A, B = 4, 2 * 10**7
+    print("[gpu] verify_range(%d, %d, 3), long unresolved list" % (A, B), flush=True)
+    g = gb.verify_range(A, B, 3, unresolved_cap=10**7, unresolved_array=True)
+    # the oracle in 16 pieces on a thread pool, merged in order
+    cuts = [A + 2 * (((B - A) // 2 + 1) * i // 16) for i in range(17)]
+    with cf.ThreadPoolExecutor(16) as ex:
+        parts = list(ex.map(lambda i: O.verify_range(cuts[i], cuts[i + 1] - 2, 3, 10**6,
+                                                     cap=10**7, seg_evens=1 << 20,
+                                                     unresolved_array=True), range(16)))
+    assert g["verified"] == sum(p["verified"] for p in parts)
+    assert g["n_unresolved"] == sum(p["n_unresolved"] for p in parts) > 8 * 10**6
+    assert g["n_failed"] == sum(p["n_failed"] for p in parts)
+    assert g["checksum"] == sum(p["checksum"] for p in parts) % (1 << 64)
+    best = max(parts, key=lambda p: (p["max_p"], -p["max_p_n"]))
+    assert (g["max_p"], g["max_p_n"]) == (best["max_p"], best["max_p_n"])
+    assert np.array_equal(g["unresolved"], np.concatenate([p["unresolved"] for p in parts]))
+    # the same emission in a batch beside other intervals, and a short list afterwards
+    ivs = [(10**9, 10**9 + 2 * 19_999), (4, 100), (10**10, 10**10 + 2 * 50_000)]
+    got = gb.verify_batch(ivs, 3, unresolved_cap=1 << 17)
+    for (a, b), r in zip(ivs, got):
+        ob = O.verify_range(a, b, 3, 10**6, cap=1 << 17)
+        for f in FIELDS:
+            assert r[f] == ob[f], (f, a, b)
+    check(gb, O, 4, 40000, 7, 10**6, cap=40000)
