@@ -49,6 +49,35 @@ __device__ __forceinline__ uint32_t gb_mod_u64_u32(uint64_t x, uint32_t p)
     return gb_mod_u64_u32_inv(x, p, gb_recip(p));
 }
 
+// Offset d in [0, p) of p's first odd multiple at or above the odd number
+// Q = 2h + 1, i.e. p | Q + 2d, for odd 3 <= p < 2^32 and h < 2^63, in double
+// precision and exactly.  Since 1/2 = (p + 1)/2 (mod p), d = (p - 1)/2 - h
+// (mod p).  The caller passes h as hh = h rounded to double and hl = h - hh
+// (|hl| <= 2^9, exact), and inv = gb_recip(p) (within an ulp of 1/p):
+//  * q = floor(hh inv) is within h 2^-50 + 1 of h / p, and q p = ph + pl
+//    exactly (the fma yields the product's rounding error);
+//  * t = (p - 1)/2 - (h - q p) = (ph - hh) + (pl + ((p - 1)/2 - hl)): each
+//    term and partial sum is an integer below 2^35 in magnitude (ph and hh lie
+//    within (h 2^-50 + 2) p + 2^11 of each other), hence exact;
+//  * f = floor(t inv) is floor(t / p) unless t is a multiple of p: |t| < 2^51
+//    keeps the estimate's error below the 1/p that separates t / p from an
+//    integer.  At a multiple, f may be one low; then d = t - f p (one exact
+//    fma) comes out as p instead of 0, which the last step maps back.
+// Contraction is off: a fused ph - hh would use the unrounded product and
+// count its rounding error twice.
+__device__ __forceinline__ uint32_t gb_first_odd_multiple(double hh, double hl, double pd,
+                                                          double inv, double half)
+{
+#pragma clang fp contract(off)
+    const double q = __builtin_floor(hh * inv);
+    const double ph = q * pd;
+    const double pl = __builtin_fma(q, pd, -ph);
+    const double t = (ph - hh) + (pl + (half - hl));
+    const double f = __builtin_floor(t * inv);
+    const uint32_t d = (uint32_t)__builtin_fma(-f, pd, t);
+    return d == (uint32_t)pd ? 0u : d;
+}
+
 // floor(sqrt(x)) exactly: a double estimate corrected with integer squares
 // that cannot wrap (the root is at most 2^32 - 1).
 __device__ __forceinline__ uint32_t gb_isqrt64(uint64_t x)

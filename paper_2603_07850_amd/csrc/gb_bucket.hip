@@ -65,38 +65,28 @@ __device__ void fill_tile(const GbBucketArgs &a, uint64_t tile)
             break;
         const uint64_t idx = (uint64_t)p_first + pi;
         const uint32_t p = a.primes[idx];
+        const double pd = (double)p;
         const double inv = gb_recip(p);
+        const double half = (double)(p >> 1);
         const uint32_t pm3 = p % 3;
         for (uint32_t cc = 0; cc < c_n; ++cc) {
             const uint32_t ci = c_first + cc;
             if (idx >= chunk[ci].p_root)
                 continue;
-            const uint64_t Q0 = chunk[ci].Q0;
             const uint64_t dmax = chunk[ci].dmax;
-            const uint64_t seg_first = chunk[ci].seg_first;
-            const uint32_t nseg = chunk[ci].nseg;
-            // Q0 mod p from one quotient estimate: Q0 / p < 2^41 here (p is a
-            // bucket prime, above 2^17), and the estimate from the rounded
-            // Q0 and the refined reciprocal is off by at most one, so the
-            // exact 64-bit residue Q0 - q p lies in (-p, 2p)
-            const double qd = __builtin_floor(chunk[ci].Q0d * inv);
-            const double qh = __builtin_floor(qd * (1.0 / 4294967296.0));
-            const uint32_t qhi = (uint32_t)qh;
-            const uint32_t qlo = (uint32_t)__builtin_fma(-qh, 4294967296.0, qd);
-            const uint64_t qp = (uint64_t)qlo * p + ((uint64_t)(qhi * p) << 32);
-            int64_t rr = (int64_t)(Q0 - qp);
-            rr += rr < 0 ? (int64_t)p : 0;
-            rr -= rr >= (int64_t)p ? (int64_t)p : 0;
-            const uint32_t r = (uint32_t)rr;
-            // first odd multiple of p at or above max(Q0, p^2), as a window
-            // bit: 2d = -Q0 (mod p)
-            const uint32_t x = r ? p - r : 0u;
-            uint64_t d = (x & 1) ? (x >> 1) + (p >> 1) + 1 : (x >> 1);
+            // first odd multiple of p at or above Q0 = 2h + 1, as a window bit
+            uint64_t d = gb_first_odd_multiple(chunk[ci].hh, chunk[ci].hl, pd, inv, half);
+            // strikes start at p^2: only a prime above isqrt(Q0) can have its
+            // square past the chunk's first odd number
             if (p > chunk[ci].sqrt_q0) {
-                const uint64_t dsq = ((uint64_t)p * p - Q0) >> 1;
+                const uint64_t dsq = ((uint64_t)p * p - chunk[ci].Q0) >> 1;
                 if (dsq > d)
                     d = dsq;
             }
+            if (d > dmax)
+                continue;
+            const uint64_t seg_first = chunk[ci].seg_first;
+            const uint32_t nseg = chunk[ci].nseg;
             // the odd number Q0 + 2d is a multiple of 3 when d = Q0 (mod 3):
             // the window does not store that class, so those bits are not struck
             const uint32_t q0m3 = chunk[ci].q0m3;

@@ -115,7 +115,8 @@ struct GbChunk {
     uint64_t dmax;        // last window bit any segment of the chunk reads
     uint32_t nseg;
     uint32_t p_root;      // one past the last table prime <= isqrt(Q0 + 2*dmax)
-    double Q0d;           // Q0 rounded to double (the quotient estimate's numerator)
+    double hh;            // h = (Q0 - 1) / 2 rounded to double
+    double hl;            // h - hh, exact (|hl| <= 2^9)
     uint32_t sqrt_q0;     // isqrt(Q0): only larger primes can have p^2 above Q0
     uint32_t q0m3;        // Q0 mod 3
 };

@@ -718,7 +718,9 @@ gb_status make_plan(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, cons
             ch.Q0 = n0 - 1 - 2ull * pl.H;                         // n0 > 2H + 2 here
             ch.dmax = (top - ch.Q0) / 2;
             ch.p_root = 0;                                        // set on the device
-            ch.Q0d = (double)ch.Q0;
+            const uint64_t h = ch.Q0 >> 1;                        // Q0 = 2h + 1
+            ch.hh = (double)h;
+            ch.hl = (double)(int64_t)(h - (uint64_t)ch.hh);
             ch.sqrt_q0 = (uint32_t)isqrt_u64(ch.Q0);
             ch.q0m3 = (uint32_t)(ch.Q0 % 3);
             if (cur.nsegs && (cur.nsegs + ns) * (uint64_t)pl.words * 4 > round_budget) {

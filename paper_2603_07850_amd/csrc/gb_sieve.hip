@@ -199,6 +199,23 @@ __device__ __forceinline__ uint32_t first_bit_d(double qd, uint32_t p)
     return jsq > j ? jsq : j;
 }
 
+// First window bit as above for a window start q_lo >= 2^52 (q_lo = 2h + 1,
+// h = hh + hl as a rounded double and its exact remainder): the first odd
+// multiple from gb_first_odd_multiple, raised to the bit of p^2 when p^2 lies
+// past q_lo (p > 2^26 here), saturated to 2^32 - 1.
+__device__ __forceinline__ uint32_t first_bit_h(double hh, double hl, uint64_t qlo, uint32_t p)
+{
+    const double pd = (double)p;
+    uint32_t j = gb_first_odd_multiple(hh, hl, pd, gb_recip(p), (double)(p >> 1));
+    const uint64_t p2 = (uint64_t)p * p;
+    if (p2 > qlo) {
+        const uint64_t jsq = (p2 - qlo) >> 1;
+        if (jsq > j)
+            j = jsq > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)jsq;
+    }
+    return j;
+}
+
 __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 {
     return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
@@ -544,9 +561,12 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
         const uint32_t x3 = neg ? (uint32_t)(qneg % 3) : (uint32_t)((3 - qlo % 3) % 3);
         const uint32_t t3 = (2 * x3) % 3;
         const ClassGeo cg = class_geo(t3, weff);
-        // windows starting in (0, 2^52) take the double-precision first-bit path
+        // windows starting in (0, 2^52) take the double-precision first-bit
+        // path, later ones the double-double one (h = (q_lo - 1) / 2 = hh + hl)
         const bool small = !neg && qlo < (1ull << 52);
         const double qd = (double)qlo;
+        const double hh = (double)(qlo >> 1);
+        const double hl = (double)(int64_t)((qlo >> 1) - (uint64_t)hh);
         if (wave == 0) {
             const uint32_t c = count_le_wave(primes, a.nprimes, gb_isqrt64(qhi), lane);
             if (lane == 0)
@@ -559,7 +579,8 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
             const uint32_t nw = nwave - kFirstStrided < kWaveN ? nwave - kFirstStrided : kWaveN;
             for (uint32_t t = tid; t < nw; t += NT) {
                 const uint32_t p = primes[kFirstStrided + t];
-                const uint32_t j0 = small ? first_bit_d(qd, p) : first_bit(qlo, qneg, neg, p);
+                const uint32_t j0 = small ? first_bit_d(qd, p)
+                                    : neg ? first_bit(qlo, qneg, neg, p) : first_bit_h(hh, hl, qlo, p);
                 uint32_t i0 = 0xFFFFFFFFu, i1 = 0xFFFFFFFFu;
                 if (j0 < weff) {
                     // j0 < weff < 2^21 and p <= 2^11: j0 + 2p < 2^23
@@ -679,6 +700,11 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                         if (pv[t])
                             strike_prime<WC>(bits, cg, weff, pv[t],
                                              first_bit_d(qd, pv[t]));
+                } else if (!neg) {
+#pragma unroll
+                    for (uint32_t t = 0; t < kPrimesInFlight; ++t)
+                        if (pv[t])
+                            strike_prime<WC>(bits, cg, weff, pv[t], first_bit_h(hh, hl, qlo, pv[t]));
                 } else {
 #pragma unroll
                     for (uint32_t t = 0; t < kPrimesInFlight; ++t)
