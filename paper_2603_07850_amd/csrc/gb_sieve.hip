@@ -174,11 +174,16 @@ __device__ __forceinline__ uint32_t first_bit(uint64_t qlo, uint64_t qneg, bool 
     return j > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)j;
 }
 
-// First window bit as above for a window start 0 < q_lo < 2^52, which a
-// double holds exactly (qd = q_lo), and p < 2^26: one double quotient
-// estimate, within one of floor(q_lo / p), and an exact fma remainder in
-// (-p, 2p) that one step corrects.
-__device__ __forceinline__ uint32_t first_bit_d(double qd, uint32_t p)
+// First window bit as above for a window start 0 < q_lo < 2^52, q_lo = 2h + 1
+// with hd = h and qd = q_lo exact doubles, and p < 2^26.  Since 1/2 = (p + 1)/2
+// (mod p), the offset is d = (p - 1)/2 - h (mod p): q = floor(hd / p) from the
+// estimate is within one of the true quotient (h / p < 2^46 keeps the
+// estimate's error far below one), q p - h is exact by one fma, so
+// t = (q p - h) + (p - 1)/2 lies in (-2p, 3p/2), and d = t - floor(t / p) p is
+// exact except that a multiple t of p may give p instead of 0.  Only a prime
+// above sq_lo = isqrt(q_lo) can have p^2 past q_lo; its bit (p^2 - q_lo)/2 is
+// exact in double (p^2 < 2^52).
+__device__ __forceinline__ uint32_t first_bit_d(double hd, double qd, uint32_t sq_lo, uint32_t p)
 {
     const double pd = (double)p;
     double inv = __builtin_amdgcn_rcp(pd);
@@ -186,30 +191,33 @@ __device__ __forceinline__ uint32_t first_bit_d(double qd, uint32_t p)
     inv = __builtin_fma(inv, e, inv);
     e = __builtin_fma(-pd, inv, 1.0);
     inv = __builtin_fma(inv, e, inv);
-    const double qt = __builtin_floor(qd * inv);
-    int32_t r = (int32_t)__builtin_fma(-qt, pd, qd);
-    r += r < 0 ? (int32_t)p : 0;
-    r -= r >= (int32_t)p ? (int32_t)p : 0;
-    const uint32_t x = r ? p - (uint32_t)r : 0u;  // -q_lo mod p
-    uint32_t j = (x & 1) ? (x >> 1) + (p >> 1) + 1 : (x >> 1);
-    // bit of p^2 when it lies past q_lo: p^2 - q_lo is exact in double (both
-    // terms below 2^52, an even integer), clamped to [0, 2^33 - 2]
-    const double dsq = __builtin_fmin(__builtin_fmax(__builtin_fma(pd, pd, -qd), 0.0), 8589934590.0);
-    const uint32_t jsq = (uint32_t)(dsq * 0.5);
-    return jsq > j ? jsq : j;
+    const double q = __builtin_floor(hd * inv);
+    const double t = __builtin_fma(q, pd, -hd) + __builtin_fma(pd, 0.5, -0.5);
+    const double f = __builtin_floor(t * inv);
+    uint32_t j = (uint32_t)__builtin_fma(-f, pd, t);
+    j = j == p ? 0u : j;
+    // a real branch (the empty asm keeps the compiler from computing the rare
+    // case for every prime)
+    if (p > sq_lo) {
+        asm volatile("" : "+v"(j));
+        const double dsq = __builtin_fmin(__builtin_fma(pd, pd, -qd) * 0.5, 4294967295.0);
+        const uint32_t jsq = (uint32_t)dsq;
+        j = jsq > j ? jsq : j;
+    }
+    return j;
 }
 
 // First window bit as above for a window start q_lo >= 2^52 (q_lo = 2h + 1,
 // h = hh + hl as a rounded double and its exact remainder): the first odd
 // multiple from gb_first_odd_multiple, raised to the bit of p^2 when p^2 lies
-// past q_lo (p > 2^26 here), saturated to 2^32 - 1.
-__device__ __forceinline__ uint32_t first_bit_h(double hh, double hl, uint64_t qlo, uint32_t p)
+// past q_lo (p > sq_lo = isqrt(q_lo) >= 2^26), saturated to 2^32 - 1.
+__device__ __forceinline__ uint32_t first_bit_h(double hh, double hl, uint64_t qlo, uint32_t sq_lo,
+                                                uint32_t p)
 {
     const double pd = (double)p;
     uint32_t j = gb_first_odd_multiple(hh, hl, pd, gb_recip(p), (double)(p >> 1));
-    const uint64_t p2 = (uint64_t)p * p;
-    if (p2 > qlo) {
-        const uint64_t jsq = (p2 - qlo) >> 1;
+    if (p > sq_lo) {
+        const uint64_t jsq = ((uint64_t)p * p - qlo) >> 1;
         if (jsq > j)
             j = jsq > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)jsq;
     }
@@ -567,6 +575,7 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
         const double qd = (double)qlo;
         const double hh = (double)(qlo >> 1);
         const double hl = (double)(int64_t)((qlo >> 1) - (uint64_t)hh);
+        const uint32_t sq_lo = neg ? 0u : gb_isqrt64(qlo);
         if (wave == 0) {
             const uint32_t c = count_le_wave(primes, a.nprimes, gb_isqrt64(qhi), lane);
             if (lane == 0)
@@ -579,8 +588,9 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
             const uint32_t nw = nwave - kFirstStrided < kWaveN ? nwave - kFirstStrided : kWaveN;
             for (uint32_t t = tid; t < nw; t += NT) {
                 const uint32_t p = primes[kFirstStrided + t];
-                const uint32_t j0 = small ? first_bit_d(qd, p)
-                                    : neg ? first_bit(qlo, qneg, neg, p) : first_bit_h(hh, hl, qlo, p);
+                const uint32_t j0 = small ? first_bit_d(hh, qd, sq_lo, p)
+                                    : neg ? first_bit(qlo, qneg, neg, p)
+                                          : first_bit_h(hh, hl, qlo, sq_lo, p);
                 uint32_t i0 = 0xFFFFFFFFu, i1 = 0xFFFFFFFFu;
                 if (j0 < weff) {
                     // j0 < weff < 2^21 and p <= 2^11: j0 + 2p < 2^23
@@ -699,12 +709,12 @@ __attribute__((amdgpu_waves_per_eu(lds_waves_per_simd(LOG2E, NT)))) void sieve_p
                     for (uint32_t t = 0; t < kPrimesInFlight; ++t)
                         if (pv[t])
                             strike_prime<WC>(bits, cg, weff, pv[t],
-                                             first_bit_d(qd, pv[t]));
+                                             first_bit_d(hh, qd, sq_lo, pv[t]));
                 } else if (!neg) {
 #pragma unroll
                     for (uint32_t t = 0; t < kPrimesInFlight; ++t)
                         if (pv[t])
-                            strike_prime<WC>(bits, cg, weff, pv[t], first_bit_h(hh, hl, qlo, pv[t]));
+                            strike_prime<WC>(bits, cg, weff, pv[t], first_bit_h(hh, hl, qlo, sq_lo, pv[t]));
                 } else {
 #pragma unroll
                     for (uint32_t t = 0; t < kPrimesInFlight; ++t)
