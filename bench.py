@@ -29,6 +29,7 @@ Extra legs (also in the JSON line):
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
                        [--no-batched] [--no-served]
        python bench.py --copy-calibration     (plain 1 GiB copies, for counters)
+       python bench.py --lds-peak             (the device's measured LDS read bandwidth)
 """
 import argparse
 import json
@@ -74,7 +75,7 @@ UNITS = (("strikes_thread_per_even", "price_strike_thread"),
          ("word_tests_per_even", "price_word_test"))
 
 
-def algorithmic_ops_per_even(wm, prices, seg_log2):
+def algorithmic_ops_per_even(wm, prices, seg_log2, section=None):
     """The method's work per even of the headline range, in 32-bit lane-ops:
     each unit the oracle counts for the kernel's geometry (strikes, first
     multiples of the sieving primes, presieve words, word-tests of the
@@ -83,7 +84,7 @@ def algorithmic_ops_per_even(wm, prices, seg_log2):
     switched off.  Lockstep waste of the probe, per-segment overhead and idle
     issue are what this leaves out.  None when no prices for the current
     kernel or no model for its segment size are at hand."""
-    cfg = wm["configs"].get(str(seg_log2))
+    cfg = (wm[section] if section else wm)["configs"].get(str(seg_log2))
     if cfg is None or prices is None:
         return None
     return sum(cfg[u] * prices[p] for u, p in UNITS)
@@ -121,8 +122,11 @@ def profile_figures():
         x = re.search(r"%s: ([0-9.]+)" % p, text)
         if x:
             prices[p] = float(x.group(1))
+    t = re.search(r"executed_word_tests_per_even: ([0-9.]+)", text)
+    if t:
+        prices["executed_word_tests_per_even"] = float(t.group(1))
     return ((int(m.group(1)) if m else None), (float(v.group(1)) if v else None),
-            prices if len(prices) == len(UNITS) else None)
+            prices if len(prices) >= len(UNITS) else None)
 
 
 def host_info():
@@ -323,10 +327,11 @@ def run_served(gb, capacity_evens_per_s, load=0.7, n_requests=2000, seed=3001):
     return out
 
 
-def run_c1(gb, steps):
+def run_c1(gb, steps, prices=None):
     """Every even n in [4, 10^10] with base primes <= 10^5: one step = table
     build + verification, launch parameters from the autotuner on the top of
-    the range."""
+    the range.  Its roofline takes the work model's units for this range and
+    the unit prices measured on the [4, 10^12] kernel."""
     import statistics
     A, B, limit = 4, 10**10, 10**5
     saved = gb.get_params()
@@ -344,9 +349,17 @@ def run_c1(gb, steps):
     gb.set_params(**saved)
     ev = evens_in(A, B)
     dt = statistics.median(each)
+    kmed = statistics.median(kern)
+    ops_even = algorithmic_ops_per_even(work_model(), prices, params["seg_log2"], "c1")
+    achieved = ops_even * ev / (kmed / 1e3) if ops_even else None
+    roof = {"bound": "alu", "achieved": achieved / 1e12 if achieved else None,
+            "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
+            "frac": achieved / VALU_PEAK_OPS if achieved else None,
+            "kernel": "sieve_probe_kernel", "kernel_ms": kmed, "ops_per_even": ops_even,
+            "prices": "measured on the [4, 1e12] kernel"}
     return {"workload": "all even n in [4, 1e10]", "base_prime_limit": limit, "params": params,
-            "evens_per_s": ev / dt, "step_s_median": dt, "kernel_ms_median": statistics.median(kern),
-            "step_cov": statistics.pstdev(each) / statistics.fmean(each),
+            "evens_per_s": ev / dt, "step_s_median": dt, "kernel_ms_median": kmed,
+            "step_cov": statistics.pstdev(each) / statistics.fmean(each), "roofline": roof,
             "result": {k: r[k] for k in ("verified", "checksum", "max_p", "max_p_n")}}
 
 
@@ -380,6 +393,7 @@ def main():
     ap.add_argument("--params", default="",
                     help="seg_log2,wg_size,window,bucket_log2 instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--lds-peak", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched launch (for profiling); needs --params")
     args = ap.parse_args()
@@ -395,6 +409,12 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.lds_peak:
+        import paper_2603_07850_amd as gb
+        gb.lib()
+        print(json.dumps({"lds_peak_bytes_per_s_16B": gb.lds_peak(16),
+                          "lds_peak_bytes_per_s_4B": gb.lds_peak(4)}), flush=True)
+        return
     if args.copy_calibration:
         copy_calibration()
         return
@@ -449,6 +469,22 @@ def main():
     ops_even = algorithmic_ops_per_even(wm, prices, st["seg_log2"])
     kern_s = sum(probe_ms) / len(probe_ms) / 1e3
     achieved = ops_even * evens / kern_s if ops_even else None
+    # LDS: the bytes the kernel moves through LDS per even (each executed
+    # word-test reads three words per lane of 64 evens; each strike reads and
+    # writes one word) against the device's measured read bandwidth for 4-byte
+    # reads (gb_lds_peak)
+    lds = None
+    if prices and "executed_word_tests_per_even" in prices:
+        cfg = wm["configs"].get(str(st["seg_log2"]))
+        lds_b = (12.0 * prices["executed_word_tests_per_even"] +
+                 8.0 * (cfg["strikes_thread_per_even"] + cfg["strikes_wave_per_even"]) +
+                 4.0 * cfg["presieve_words_per_even"]) if cfg else None
+        peak4 = gb.lds_peak(4)
+        peak16 = gb.lds_peak(16)
+        if lds_b:
+            lds = {"bytes_per_even": lds_b, "achieved_GBps": lds_b * evens / kern_s / 1e9,
+                   "peak_GBps_4B_reads": peak4 / 1e9, "peak_GBps_16B_reads": peak16 / 1e9,
+                   "frac": lds_b * evens / kern_s / peak4}
     roofline = {"bound": "alu",
                 "achieved": achieved / 1e12 if achieved else None,
                 "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
@@ -458,7 +494,8 @@ def main():
                 "ops_per_even": ops_even,
                 # the issue roofline from the counters: VALU instructions issued
                 # over the peak of one wave64 instruction per CU per cycle
-                "valu_issue_frac": valu_issue}
+                "valu_issue_frac": valu_issue,
+                "lds": lds}
 
     out = {
         "metric": "even n verified/sec at 1 GPU (to 1e12)",
@@ -478,7 +515,7 @@ def main():
         "roofline": roofline,
         "timing": timing,
     }
-    out["c1"] = run_c1(gb, args.steps)
+    out["c1"] = run_c1(gb, args.steps, prices)
     if not args.no_batched:
         # batches reach 2^64: their launch parameters come from the batch
         # autotuner on every 8th interval of the batch (unless --params)

@@ -452,6 +452,18 @@ gb_status gb_release(void);
 /* Message for the last failing call on this thread ("" if none). */
 const char *gb_last_error(void);
 
+/*
+ * Measurement support for the roofline of the segment kernel (paper Sec. 4.3,
+ * profiling validation): the LDS read bandwidth of the current device,
+ * measured with conflict-free reads of `width` bytes per lane (16: the LDS
+ * data path's width; 4: the probe's word reads) by two 1024-thread workgroups
+ * per CU, each reading its own 64 KiB of LDS 20000 times over; *bytes_per_s is
+ * the whole device's rate.  Runs on the null stream and waits for it;
+ * allocates 4 bytes per workgroup for the duration of the call.  GB_EINVAL for
+ * another width or a NULL output, GB_EHIP when a HIP call fails.
+ */
+gb_status gb_lds_peak(uint32_t width, double *bytes_per_s);
+
 #ifdef __cplusplus
 }
 #endif

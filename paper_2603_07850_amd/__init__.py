@@ -7,7 +7,7 @@ the ``_binding`` module only marshals arguments to its C ABI
 library is missing.  Attributes are resolved lazily so that importing the
 ``workloads`` submodule does not touch the binding.
 """
-_API = ("GoldbachError", "Params", "Server", "autotune", "autotune_batch", "autotune_cache_clear", "base_primes", "debug_fail_next", "get_params", "is_prime_u64",
+_API = ("GoldbachError", "Params", "Server", "autotune", "autotune_batch", "autotune_cache_clear", "base_primes", "debug_fail_next", "get_params", "is_prime_u64", "lds_peak",
         "last_stats", "last_batch_latencies", "lib", "release", "set_params", "table_count", "table_limit", "table_read",
         "verify_batch", "verify_range", "verify_range_noalloc", "set_allocator",
         "verify_range_u128", "is_prime_u128", "AsyncVerify",

@@ -110,6 +110,7 @@ def lib():
         "gb_is_prime_u64": (st, [vp, u64, vp, vp]),
         "gb_last_stats": (st, [ctypes.POINTER(Stats)]),
         "gb_debug_fail_next": (st, [ctypes.c_uint32]),
+        "gb_lds_peak": (st, [ctypes.c_uint32, ctypes.POINTER(ctypes.c_double)]),
         "gb_last_latencies": (st, [vp, u64]),
         "gb_server_open": (st, [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
         "gb_server_submit": (st, [vp, u64, u64, ctypes.POINTER(u64)]),
@@ -345,6 +346,14 @@ def is_prime_u64(q):
     _check(lib().gb_is_prime_u64(q.data_ptr(), q.numel(), out.data_ptr(),
                                  torch.cuda.current_stream(q.device).cuda_stream))
     return out
+
+
+def lds_peak(width=16):
+    """gb_lds_peak: the device's measured LDS read bandwidth in bytes/s for
+    `width`-byte reads per lane (16 or 4)."""
+    out = ctypes.c_double(0)
+    _check(lib().gb_lds_peak(int(width), ctypes.byref(out)))
+    return out.value
 
 
 def debug_fail_next(where):

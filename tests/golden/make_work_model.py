@@ -20,13 +20,17 @@ The p_min come from the oracle; the strike counts are exact counts of
 multiples in each sampled window.  Sampled segments are spread uniformly over
 the range (the range is uniform in n).
 
+With --c1 it adds (or replaces) the "c1" section only: the same units for
+every even n in [4, 10^10] with base primes <= 10^5 and probe window 16384,
+per segment size.
+
 With --batch it adds (or replaces) the "batch" section only: for the seeded
 batch of 4096 intervals, the first-multiple computations the strike-bitmap
 method must make, one per table prime p with bound < p <= isqrt(top) per
 interval (an interval's prime must be located once; all its later multiples
 follow by adding p), per even, for bitmap bounds 2^21 .. 2^25.
 
-Run:  python tests/golden/make_work_model.py [--batch]
+Run:  python tests/golden/make_work_model.py [--c1 | --batch]
 """
 import json
 import math
@@ -60,7 +64,7 @@ def odd_multiples(p, lo, hi):
     return np.maximum(f(hi // p) - f((lo + p - 1) // p - 1), 0)
 
 
-def segment_counts(n0, cnt, E, H, primes, cand):
+def segment_counts(n0, cnt, E, H, primes, cand, limit=LIMIT):
     """Strikes (wave tier, thread tier), presieve words and word-tests of one segment."""
     weff = cnt - 1 + H
     qlo = n0 - 1 - 2 * H
@@ -78,7 +82,7 @@ def segment_counts(n0, cnt, E, H, primes, cand):
     fm_thread = int(np.count_nonzero(p > E // 512))
     words = 2 * ((weff + 95) // 96 + 1)
     # word-tests from the oracle's p_min
-    r = O.verify_range(n0, n0 + 2 * (cnt - 1), 65536, LIMIT, want_pmin=True)
+    r = O.verify_range(n0, n0 + 2 * (cnt - 1), 65536, limit, want_pmin=True)
     pm = np.asarray(r["pmin"], dtype=np.int64)
     n = n0 + 2 * np.arange(cnt, dtype=np.int64)
     tests = 0
@@ -96,21 +100,21 @@ def segment_counts(n0, cnt, E, H, primes, cand):
     return wave, thread, words, tests, fm_wave, fm_thread
 
 
-def model(seg_log2, rng):
+def model(seg_log2, rng, rng_range=RANGE, limit=LIMIT, window=WINDOW):
     E = 1 << seg_log2
-    H = halo(WINDOW)
-    primes = O.primes(LIMIT)
+    H = halo(window)
+    primes = O.primes(limit)
     cand = O.primes(65536)[1:].astype(np.int64)
-    cand = cand[cand <= WINDOW]
-    nseg = ((RANGE[1] - RANGE[0]) // 2 + 1 + E - 1) // E
+    cand = cand[cand <= window]
+    nseg = ((rng_range[1] - rng_range[0]) // 2 + 1 + E - 1) // E
     tot = np.zeros(6, dtype=np.float64)
     ev = 0
     for s in rng.choice(np.arange(1, nseg - 1), size=SAMPLES, replace=False):
-        n0 = RANGE[0] + 2 * E * int(s)
-        tot += segment_counts(n0, E, E, H, primes, cand)
+        n0 = rng_range[0] + 2 * E * int(s)
+        tot += segment_counts(n0, E, E, H, primes, cand, limit)
         ev += E
     w, t, wd, ts, fw, ft = tot / ev
-    return {"seg_log2": seg_log2, "halo_bits": H, "window": WINDOW, "segments_sampled": SAMPLES,
+    return {"seg_log2": seg_log2, "halo_bits": H, "window": window, "segments_sampled": SAMPLES,
             "evens_sampled": ev, "strikes_wave_per_even": w, "strikes_thread_per_even": t,
             "first_multiples_wave_per_even": fw, "first_multiples_thread_per_even": ft,
             "presieve_words_per_even": wd, "word_tests_per_even": ts}
@@ -136,6 +140,19 @@ def batch_section():
 
 
 def main():
+    if "--c1" in sys.argv:
+        path = os.path.join(HERE, "work_model.json")
+        with open(path) as f:
+            out = json.load(f)
+        rng = np.random.default_rng(1010)
+        out["c1"] = {"range": [4, 10**10], "base_prime_limit": 10**5,
+                     "configs": {str(lg): model(lg, rng, (4, 10**10), 10**5, 16384)
+                                 for lg in (18, 19, 20)}}
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+            f.write("\n")
+        print(json.dumps(out["c1"], indent=1))
+        return
     if "--batch" in sys.argv:
         path = os.path.join(HERE, "work_model.json")
         with open(path) as f:
