@@ -286,8 +286,9 @@ gb_status gb_get_params(gb_params *p);
 
 /*
  * Autotuner: time a calibration run of [A, B] (at most 2^36 evens) under each
- * segment size, workgroup size and probe window (and, when isqrt(B) > 2^22,
- * with and without strike bitmaps), keep the fastest as the current parameters
+ * segment size (2^18, 2^19, 2^20 evens), workgroup size (256, 512, 1024) and
+ * probe window (2^12, 2^14, 2^16) (and, when isqrt(B) > 2^22, with and without
+ * strike bitmaps), keep the fastest as the current parameters
  * and write it to *best (may be NULL).  Results of later calls do not depend
  * on the choice.  Built for full ranges [4, N] as in the paper's Table 1
  * (N = 10^10 and 10^12 here): the calibration range is the top of the range.

@@ -1750,7 +1750,7 @@ gb_status tune(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, hipStream
     const gb_params saved = c.params;
     const uint32_t logs[3] = {18, 19, 20};
     const uint32_t wgs[3] = {256, 512, 1024};
-    const uint32_t wins[2] = {4096, 16384};
+    const uint32_t wins[3] = {4096, 16384, 65536};   // the probe windows 2^12, 2^14, 2^16
     double best_t = 1e300;
     gb_params best_p = saved;
     std::vector<gb_result> out(k);
@@ -1767,7 +1767,7 @@ gb_status tune(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, hipStream
                     }
                     c.params = p;
                     double tmin = 1e300;
-                    for (int rep = 0; rep < 2; ++rep) {
+                    for (int rep = 0; rep < 3; ++rep) {   // the fastest of three runs
                         const auto t0 = std::chrono::steady_clock::now();
                         gb_status st = verify_many(c, AB, k, P_max, s, out.data(), false);
                         const auto t1 = std::chrono::steady_clock::now();
