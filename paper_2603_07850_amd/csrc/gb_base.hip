@@ -73,14 +73,15 @@ __global__ __launch_bounds__(kSeedThreads) void seed_kernel(uint32_t *seed, uint
     __syncthreads();
     if (t == 0)
         atomicAnd(&bits[0], ~1u);  // 1 is not prime
-    // odd p < 256 strike their odd multiples from p^2; p^2 < 2^16 needs p <= 255
-    if (t < 127) {
-        const uint32_t p = 2 * t + 3;
-        if (small_is_prime(p))
-            for (uint32_t m = p * p; m < kSeedLimit; m += 2 * p) {
-                const uint32_t b = m >> 1;
-                atomicAnd(&bits[b >> 5], ~(1u << (b & 31)));
-            }
+    // odd p < 256 strike their odd multiples from p^2 (p^2 < 2^16 needs
+    // p <= 255), the whole workgroup taking each prime's multiples in turn
+    for (uint32_t p = 3; p < 256; p += 2) {
+        if (!small_is_prime(p))
+            continue;
+        for (uint32_t m = p * p + 2 * p * t; m < kSeedLimit; m += 2 * p * kSeedThreads) {
+            const uint32_t b = m >> 1;
+            atomicAnd(&bits[b >> 5], ~(1u << (b & 31)));
+        }
     }
     __syncthreads();
     const uint32_t w = bits[t];

@@ -265,6 +265,25 @@ bool params_valid(const gb_params &p)
     return p.wg_per_cu <= 64 && p.bucket_mib <= (1u << 20);
 }
 
+// The prime and candidate tables alone, and the captured graph that holds
+// their addresses; nothing of the library may still be running on them.
+void release_tables(Ctx &c)
+{
+    if (c.device >= 0 && c.primes.p)
+        (void)hipDeviceSynchronize();
+    c.async_pending = false;
+    c.primes.release();
+    c.d_ctab.release();
+    c.d_ptab.release();
+    c.small.clear();
+    c.T = 0;
+    c.nprimes = 0;
+    c.graph_key.clear();
+    if (c.graph_exec)
+        (void)hipGraphExecDestroy(c.graph_exec);
+    c.graph_exec = nullptr;
+}
+
 void release_all(Ctx &c)
 {
     // memory may go back to a caching allocator that hands it out again at
@@ -328,9 +347,14 @@ gb_status build_table(Ctx &c, uint64_t limit)
 {
     int dev = 0;
     GB_HIP(hipGetDevice(&dev));
-    hipDeviceProp_t prop;
-    GB_HIP(hipGetDeviceProperties(&prop, dev));
-    release_all(c);
+    int ncu = 0;
+    GB_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    // a table on the same device keeps the verification workspaces (sized for
+    // earlier calls, they stay valid); on another device everything goes
+    if (c.device == dev)
+        release_tables(c);
+    else
+        release_all(c);
     if (dev < 0 || dev >= kMaxDevices) {
         set_err("device index %d is outside the supported 0..%d", dev, kMaxDevices - 1);
         return GB_EINVAL;
@@ -348,7 +372,7 @@ gb_status build_table(Ctx &c, uint64_t limit)
         g_scratch[dev] = ptr;
     }
     c.device = dev;
-    c.num_cu = prop.multiProcessorCount;
+    c.num_cu = ncu;
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
         c.wall_khz = khz;
@@ -1124,7 +1148,21 @@ gb_status verify_many(Ctx &c, const uint64_t *AB, uint64_t k, uint64_t P_max, hi
     Plan pl;
     uint64_t spills = 0;
     GB_TRY(make_plan(c, AB, k, P_max, pr, pl));
+    // A spill list grown by an earlier call (tiny P_max) is kept, but its
+    // ordered listing needs one bit per even of the batch; where that bitmap
+    // would exceed its limit, this call starts from the pairwise ranking's
+    // 2^16 entries and grows only if its own spills need it.
+    const uint64_t grown = c.spill_cap;
+    if (c.spill_cap > kRankEmitMax) {
+        uint64_t words = 0;
+        for (const GbInterval &g : pl.dev_iv)
+            words += (g.nE + 31) / 32;
+        if (words * 4 > kEmitBitmapMaxBytes)
+            c.spill_cap = kRankEmitMax;
+    }
     GB_TRY(run_once(c, pl, P_max, pr, s, use_graph, &spills));
+    if (spills <= c.spill_cap)
+        c.spill_cap = std::max(c.spill_cap, grown);
     if (spills > c.spill_cap) {
         // the count is exact (every append counts, stored or not), so one
         // rerun with room for all of them completes the call

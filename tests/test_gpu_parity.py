@@ -433,3 +433,24 @@ def test_tiny_pmax_long_range(gb, O):
         for f in FIELDS:
             assert r[f] == ob[f], (f, a, b)
     check(gb, O, 4, 40000, 7, 10**6, cap=40000)
+
+
+def test_grown_spill_list_then_long_range(gb):
+    """A spill list grown by a tiny-P_max call stays with the library; a later
+    range too long for the ordered listing of that many entries (one bit per
+    even: 7.5e10 evens would take 8.7 GiB) starts again from 2^16 entries and
+    completes exactly (results equal to the same call after gb_release and a
+    fresh table, which start from scratch)."""
+    table(gb, 10**6)
+    print("[gpu] tiny P_max to grow the spill list", flush=True)
+    gb.verify_range(4, 2 * 10**6, 3)
+    A, B = 4, 150 * 10**9
+    print("[gpu] verify_range(%d, %d, 65536) after it" % (A, B), flush=True)
+    g = gb.verify_range(A, B, 65536)
+    assert g["verified"] == (B - A) // 2 + 1 and g["n_unresolved"] == 0 and g["n_failed"] == 0
+    gb.release()
+    _current["limit"] = None
+    table(gb, 10**6)
+    fresh = gb.verify_range(A, B, 65536)
+    for f in FIELDS:
+        assert g[f] == fresh[f], f
