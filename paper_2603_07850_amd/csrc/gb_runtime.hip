@@ -265,17 +265,16 @@ bool params_valid(const gb_params &p)
     return p.wg_per_cu <= 64 && p.bucket_mib <= (1u << 20);
 }
 
-// The prime and candidate tables alone, and the captured graph that holds
-// their addresses; nothing of the library may still be running on them.
+// Before a table is rebuilt on the same device: the captured graph (it holds
+// the table's address) goes, and the table counts as absent until the build
+// ends.  The buffers stay: the prime table's is reused when large enough, and
+// the candidate tables (from the primes below 2^16, the same for every table)
+// are kept as they are.  Nothing of the library may still be running.
 void release_tables(Ctx &c)
 {
     if (c.device >= 0 && c.primes.p)
         (void)hipDeviceSynchronize();
     c.async_pending = false;
-    c.primes.release();
-    c.d_ctab.release();
-    c.d_ptab.release();
-    c.small.clear();
     c.T = 0;
     c.nprimes = 0;
     c.graph_key.clear();
@@ -450,8 +449,12 @@ gb_status build_table(Ctx &c, uint64_t limit)
         return GB_EHIP;
     }
     const uint64_t nsmall = std::min<uint64_t>(c.nprimes, 6542);  // pi(65536)
-    c.small.resize(nsmall);
     counts.release();
+    // every table holds the primes below 2^16 (T >= 2^16): the host copy and
+    // the candidate tables built from them are made once per device
+    if (c.small.size() == nsmall && c.d_ctab.p && c.d_ptab.p)
+        return GB_OK;
+    c.small.resize(nsmall);
     e = hipMemcpy(c.small.data(), c.primes.p, nsmall * 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
         set_err("prime table copy failed: %s", hipGetErrorString(e));
