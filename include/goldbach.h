@@ -460,8 +460,8 @@ const char *gb_last_error(void);
  * data path's width; 4: the probe's word reads) by two 1024-thread workgroups
  * per CU, each reading its own 64 KiB of LDS 20000 times over; *bytes_per_s is
  * the whole device's rate.  Runs on the null stream and waits for it;
- * allocates 4 bytes per workgroup for the duration of the call.  GB_EINVAL for
- * another width or a NULL output, GB_EHIP when a HIP call fails.
+ * allocates no device memory.  GB_EINVAL for another width or a NULL output,
+ * GB_EHIP when a HIP call fails.
  */
 gb_status gb_lds_peak(uint32_t width, double *bytes_per_s);
 
