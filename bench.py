@@ -23,6 +23,8 @@ Extra legs (also in the JSON line):
                 batching server and through one gb_verify_range at a time, at
                 0.7x the batched capacity and saturated, every served result
                 compared with the request verified alone;
+  past_2_64     windows of 2^22 evens just above 2^64, at 2^96 and below 2^128
+                through gb_verify_range_u128 (Baillie-PSW past 2^64);
   cpu_baseline  the CPU oracle on this host's cores over seeded 10^7-wide
                 windows of the headline range, plus single-thread rates.
 
@@ -145,8 +147,9 @@ def host_info():
 def cpu_baseline(sample_windows):
     """The oracle, as it stands: aggregate over seeded windows of the headline
     range on the host's cores (at most 16: the CPU share of one GPU on the
-    box), and single-thread rates on [4, 10^8], a 10^7-wide window near 10^12
-    and 2^24 evens ending at 2^64 - 2."""
+    box), and single-thread rates on [4, 10^8], a 10^7-wide window near 10^12,
+    2^24 evens ending at 2^64 - 2 and 2^12 evens from 2^64 (the wide oracle,
+    Baillie-PSW)."""
     from concurrent.futures import ThreadPoolExecutor
 
     from oracle import oracle as O
@@ -171,6 +174,9 @@ def cpu_baseline(sample_windows):
         t1 = time.perf_counter()
         r = O.verify_range(a, b, HEADLINE["P_max"], limit, seg_evens=seg)
         single[label] = r["verified"] / (time.perf_counter() - t1)
+    t1 = time.perf_counter()
+    r = O.verify_range_wide(1 << 64, (1 << 64) + 2 * 4095, HEADLINE["P_max"], 10**7)
+    single["2^12 evens from 2^64 (Baillie-PSW)"] = r["verified"] / (time.perf_counter() - t1)
     return {"value": ev / dt, "unit": "even n verified/s", "cores": cores, "kind": "oracle",
             "sample": "%d seeded 1e7-wide windows of [4, 1e12] (%d evens), %d threads, %.1f s wall"
                       % (len(wins), ev, cores, dt),
@@ -363,6 +369,27 @@ def run_c1(gb, steps, prices=None):
             "result": {k: r[k] for k in ("verified", "checksum", "max_p", "max_p_n")}}
 
 
+def run_past_2_64(gb, steps=3):
+    """Windows of 2^22 evens past the 64-bit ceiling (base primes <= 2^32 - 1
+    resident, P_max = 2^16): evens/s of gb_verify_range_u128 (median of
+    `steps`).  The wide oracle's single-thread rate is in cpu_baseline."""
+    import statistics
+    n = 1 << 22
+    out = {"evens_per_window": n}
+    for label, A in (("2^64", 1 << 64), ("2^96", 1 << 96), ("2^128 - 2^23", (1 << 128) - 2 * n - 2)):
+        B = A + 2 * (n - 1)
+        r = gb.verify_range_u128(A, B, 65536)
+        each = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            r2 = gb.verify_range_u128(A, B, 65536)
+            each.append(time.perf_counter() - t0)
+        dt = statistics.median(each)
+        out[label] = {"evens_per_s": n / dt, "s_median": dt, "consistent": r2 == r,
+                      "all_verified": r["verified"] == n and r["n_failed"] == 0}
+    return out
+
+
 def copy_calibration():
     import torch
     n = 1 << 30
@@ -396,6 +423,8 @@ def main():
     ap.add_argument("--lds-peak", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched launch (for profiling); needs --params")
+    ap.add_argument("--past-2-64-only", action="store_true",
+                    help="only the windows past 2^64 (for profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -426,6 +455,10 @@ def main():
         gb.set_params(seg_log2=lg, wg_size=wg, window=win, bucket_log2=blog)
         print(json.dumps({"batched": run_batched(gb, args.steps, per_interval=False),
                           "params": gb.get_params()}), flush=True)
+        return
+    if args.past_2_64_only:
+        gb.base_primes(2**32 - 1)
+        print(json.dumps({"past_2_64": run_past_2_64(gb, args.steps)}), flush=True)
         return
     A, B, P_max, limit = HEADLINE["A"], HEADLINE["B"], HEADLINE["P_max"], HEADLINE["limit"]
     evens = evens_in(A, B)
@@ -526,6 +559,9 @@ def main():
         out["batched"] = run_batched(gb, 5, tune=not args.params)
     if not args.no_batched and not args.no_served:
         out["served"] = run_served(gb, out["batched"]["batched_evens_per_s"])
+    if not args.no_batched:
+        # the 2^32 table of the batched leg is resident
+        out["past_2_64"] = run_past_2_64(gb)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_windows)
         out["vs_cpu_baseline"] = value / out["cpu_baseline"]["value"]
