@@ -231,6 +231,17 @@ gb_status gb_verify_range_u128(uint64_t A_lo, uint64_t A_hi, uint64_t B_lo, uint
                                uint64_t P_max, void *stream, gb_result128 *out);
 
 /*
+ * Evens per chunk of a range past 2^64: gb_verify_range_u128 sieves and
+ * probes such a range chunk after chunk, each chunk with a strike bitmap of
+ * 2^log2 + H bits in device memory (H <= 32768 halo bits below the chunk's
+ * first n).  log2 in [12, 30]; 26 by default (an 8 MiB bitmap).  Results do not
+ * depend on it; fewer, longer chunks keep more lanes busy at each chunk's end.
+ * GB_EINVAL outside the range.  Applies to later calls.
+ */
+gb_status gb_set_wide_chunk_log2(uint32_t log2);
+gb_status gb_get_wide_chunk_log2(uint32_t *log2);
+
+/*
  * Primality of `count` u128 values q[2i] + 2^64 q[2i+1] (DEVICE pointers:
  * 16 * count and count bytes): the deterministic Miller-Rabin test below 2^64
  * and Baillie-PSW above, the tests of gb_verify_range_u128, exported so that

@@ -10,7 +10,8 @@ library is missing.  Attributes are resolved lazily so that importing the
 _API = ("GoldbachError", "Params", "Server", "autotune", "autotune_batch", "autotune_cache_clear", "base_primes", "debug_fail_next", "get_params", "is_prime_u64", "lds_peak",
         "last_stats", "last_batch_latencies", "lib", "release", "set_params", "table_count", "table_limit", "table_read",
         "verify_batch", "verify_range", "verify_range_noalloc", "set_allocator",
-        "verify_range_u128", "is_prime_u128", "AsyncVerify",
+        "verify_range_u128", "is_prime_u128", "AsyncVerify", "set_wide_chunk_log2",
+        "get_wide_chunk_log2",
         "use_torch_allocator", "RESULT_FIELDS")
 
 

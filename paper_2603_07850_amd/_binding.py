@@ -104,6 +104,8 @@ def lib():
         "gb_set_allocator": (st, [ALLOC_FN, FREE_FN, vp]),
         "gb_set_params": (st, [ctypes.POINTER(Params)]),
         "gb_get_params": (st, [ctypes.POINTER(Params)]),
+        "gb_set_wide_chunk_log2": (st, [ctypes.c_uint32]),
+        "gb_get_wide_chunk_log2": (st, [ctypes.POINTER(ctypes.c_uint32)]),
         "gb_autotune": (st, [u64, u64, u64, vp, ctypes.POINTER(Params)]),
         "gb_autotune_batch": (st, [ctypes.POINTER(ctypes.c_uint64), u64, u64, vp, ctypes.POINTER(Params)]),
         "gb_autotune_cache_clear": (st, []),
@@ -313,6 +315,17 @@ def get_params():
     p = Params()
     _check(lib().gb_get_params(ctypes.byref(p)))
     return p.as_dict()
+
+
+def set_wide_chunk_log2(log2):
+    """gb_set_wide_chunk_log2: evens per chunk (2^log2) of ranges past 2^64."""
+    _check(lib().gb_set_wide_chunk_log2(int(log2)))
+
+
+def get_wide_chunk_log2():
+    v = ctypes.c_uint32()
+    _check(lib().gb_get_wide_chunk_log2(ctypes.byref(v)))
+    return int(v.value)
 
 
 def autotune(A, B, P_max, stream=None):

@@ -183,8 +183,9 @@ struct Ctx {
     HostBuf h_woff;
     std::vector<uint64_t> last_slot;    // last call: caller's index -> kernel slot
     // workspaces of the verification past 2^64
-    DevBuf d_wrec, d_wspill, d_wres, d_wunres, d_wctr;
+    DevBuf d_wrec, d_wspill, d_wres, d_wunres, d_wctr, d_wbits;
     HostBuf h_wres;
+    uint32_t wide_chunk_log2 = kWideChunkLog2Default;   // evens per chunk past 2^64
     // stream-ordered calls: the gb_result image they copy out, and the event
     // that ends the last one's use of the shared workspaces
     DevBuf d_async;
@@ -330,6 +331,7 @@ void release_all(Ctx &c)
     c.d_wres.release();
     c.d_wunres.release();
     c.d_wctr.release();
+    c.d_wbits.release();
     c.h_wres.release();
     c.small.clear();
     for (auto &e : c.ev)
@@ -1431,12 +1433,17 @@ gb_status verify_wide_part(Ctx &c, u128h A, u128h B, uint64_t P_max, hipStream_t
     const uint32_t hmax = ncand ? (c.small[ncand] - 1) / 2 : 0;
     const uint32_t H = std::max<uint32_t>(32, (hmax + 31) / 32 * 32);
     const uint64_t nsieve = c.T >= (1ull << kWideSieveLog2) ? c.pi2[kWideSieveLog2] : c.nprimes;
-    const uint64_t nsegs = (nE + (1ull << kWideLog2E) - 1) >> kWideLog2E;
-    GB_TRY(c.d_wrec.reserve(nsegs * sizeof(GbWideRecord)));
+    const uint64_t chunk = 1ull << c.wide_chunk_log2;
+    const uint64_t nchunks = (nE + chunk - 1) / chunk;
+    const uint32_t occ = (uint32_t)gb_wide_occupancy();
+    const uint32_t nrec = (uint32_t)c.num_cu * occ;
+    const uint64_t max_words = (std::min<uint64_t>(nE, chunk) + H + 31) / 32;
+    GB_TRY(c.d_wrec.reserve((uint64_t)nrec * sizeof(GbWideRecord)));
     GB_TRY(c.d_wspill.reserve(kWideSpillCap * sizeof(GbWideSpill)));
     GB_TRY(c.d_wunres.reserve(kWideSpillCap * sizeof(u128w)));
     GB_TRY(c.d_wres.reserve(sizeof(GbWideResult)));
     GB_TRY(c.d_wctr.reserve(64));
+    GB_TRY(c.d_wbits.reserve(max_words * 4));
     GB_TRY(c.h_wres.reserve(sizeof(GbWideResult)));
     for (auto &e : c.ev)
         if (!e)
@@ -1447,22 +1454,47 @@ gb_status verify_wide_part(Ctx &c, u128h A, u128h B, uint64_t P_max, hipStream_t
     a.nsieve = (uint32_t)nsieve;
     a.ncand = ncand;
     a.H = H;
+    // primes[1 ..) below 2^16 and below 2^12 (every table holds the primes below 2^16)
+    a.nsmall = (uint32_t)std::min<uint64_t>(nsieve, small_count_le(c, 65535));
+    a.ncoop = (uint32_t)std::min<uint64_t>(a.nsmall, small_count_le(c, 4095));
+    a.nrec = nrec;
     a.A.lo = (uint64_t)A;
     a.A.hi = (uint64_t)(A >> 64);
     a.nE = nE;
-    a.nsegs = nsegs;
     a.rec = (GbWideRecord *)c.d_wrec.p;
     a.spill = (GbWideSpill *)c.d_wspill.p;
     a.spill_cap = kWideSpillCap;
     a.ctr = (unsigned long long *)c.d_wctr.p;
-    const uint32_t grid =
-        (uint32_t)std::min<uint64_t>(nsegs, (uint64_t)c.num_cu * (uint64_t)gb_wide_occupancy());
+    const uint32_t fill_grid =
+        nsieve > a.nsmall ? (uint32_t)std::min<uint64_t>((nsieve - a.nsmall + 255) / 256,
+                                                         (uint64_t)c.num_cu * 8)
+                          : 0;
+    uint32_t grid_max = 0;
     gb_status st = GB_OK;
     auto launch = [&]() -> gb_status {
         GB_HIP(hipEventRecord(c.ev[0], s));
-        GB_HIP(gb_launch_wide_reset(a.ctr, s));
+        GB_HIP(gb_launch_wide_reset(a, s));
         GB_HIP(hipEventRecord(c.ev[1], s));
-        GB_HIP(gb_launch_wide(a, grid, s));
+        for (uint64_t ci = 0; ci < nchunks; ++ci) {
+            GbWideChunk ch = {};
+            const uint64_t i0 = ci * chunk;
+            ch.cnt = (uint32_t)std::min<uint64_t>(chunk, nE - i0);
+            ch.nbits = ch.cnt + H;
+            const u128h n0 = A + 2 * (u128h)i0;
+            const u128h q0 = n0 - 1 - 2 * (u128h)H;   // n0 >= 2^64: no wrap
+            ch.n0.lo = (uint64_t)n0;
+            ch.n0.hi = (uint64_t)(n0 >> 64);
+            ch.qlo.lo = (uint64_t)q0;
+            ch.qlo.hi = (uint64_t)(q0 >> 64);
+            ch.bits = (uint32_t *)c.d_wbits.p;
+            const uint64_t words = (ch.nbits + 31) / 32;
+            const uint32_t sieve_grid = (uint32_t)std::min<uint64_t>(
+                (words + kWideSieveWords - 1) / kWideSieveWords, (uint64_t)c.num_cu * 8);
+            // a block per 256 evens at most, so that a short chunk claims no idle blocks
+            const uint32_t grid = (uint32_t)std::min<uint64_t>(nrec, (ch.cnt + 255) / 256);
+            grid_max = std::max(grid_max, grid);
+            GB_HIP(gb_launch_wide_chunk(a, ch, sieve_grid, fill_grid, grid, s));
+        }
         GB_HIP(hipEventRecord(c.ev[2], s));
         GB_HIP(gb_launch_wide_phase2(a, (uint32_t)c.num_cu * 4, s));
         GB_HIP(gb_launch_wide_reduce(a, P_max, (GbWideResult *)c.d_wres.p, (u128w *)c.d_wunres.p, s));
@@ -1490,12 +1522,12 @@ gb_status verify_wide_part(Ctx &c, u128h A, u128h B, uint64_t P_max, hipStream_t
     stt = gb_stats{};
     stt.probe_ms = pm;
     stt.total_ms = tot;
-    stt.segments = nsegs;
+    stt.segments = nchunks;
     stt.evens = nE;
     stt.spills = r.spills;
-    stt.grid = grid;
+    stt.grid = grid_max;
     stt.wg_size = kWideThreads;
-    stt.seg_log2 = kWideLog2E;
+    stt.seg_log2 = c.wide_chunk_log2;
     stt.halo_bits = H;
     stt.ncand = ncand;
     stt.intervals = 1;
@@ -1765,6 +1797,33 @@ gb_status gb_set_params(const gb_params *p)
         return GB_EINVAL;
     }
     c.params = *p;
+    return GB_OK;
+}
+
+gb_status gb_set_wide_chunk_log2(uint32_t log2)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    g_err.clear();
+    if (log2 < kWideChunkLog2Min || log2 > kWideChunkLog2Max) {
+        set_err("the chunk size past 2^64 must be 2^%u .. 2^%u evens (got 2^%u)",
+                kWideChunkLog2Min, kWideChunkLog2Max, log2);
+        return GB_EINVAL;
+    }
+    c.wide_chunk_log2 = log2;
+    return GB_OK;
+}
+
+gb_status gb_get_wide_chunk_log2(uint32_t *log2)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    g_err.clear();
+    if (!log2) {
+        set_err("null output");
+        return GB_EINVAL;
+    }
+    *log2 = c.wide_chunk_log2;
     return GB_OK;
 }
 

@@ -2,24 +2,30 @@
 // of Sec. 5: 128-bit sieve arithmetic coupled with a Baillie-PSW test).
 //
 // Beyond 2^64 the table of primes up to 2^32 no longer reaches sqrt(q), so the
-// segment window is a pre-filter: a persistent kernel claims segments of
-// 2^16 evens, strikes from the LDS window every odd q = n - p with a prime
-// factor up to the sieve bound S (the table primes up to min(T, 2^28); the
-// window start is a 128-bit number, so each prime's first multiple comes from
-// a 128-by-32 remainder), and then decides the survivors, in ascending p for
-// each n, with the Baillie-PSW test.  The first survivor that passes gives
-// p_min(n).  Survivors are prime with probability about 0.9, so an even costs
-// about one Baillie-PSW test, and a wave keeps all its lanes busy by handing
-// a finished lane the next even of its share (no lockstep over a block).
-// Evens that no candidate p <= P_max resolves are spilled to the wide
-// Phase-2 kernel, which continues with the table primes above P_max.
+// sieve is a pre-filter: it marks every odd q = n - p with a prime factor up to
+// the sieve bound S (the table primes up to min(T, 2^28)), and the survivors
+// are decided, in ascending p for each n, by the Baillie-PSW test; the first
+// survivor that passes gives p_min(n).  A range is taken in chunks of up to
+// 2^26 evens (a runtime setting), each with a strike bitmap in device memory
+// over the odd numbers from n0 - 1 - 2H, and three kernels per chunk:
+//   * the primes below 2^16 strike 2^15-bit passes of the bitmap in LDS
+//     (below 2^12 a whole wave per prime, above one thread per prime), and
+//     each pass is written out as whole words;
+//   * the larger sieving primes, one thread each, locate their first multiple
+//     once per chunk (a 128-by-32 remainder) and OR their strikes into the
+//     bitmap with device atomics (a few per thousand bits each);
+//   * a persistent probe over all CUs: a lane holds one even and its next
+//     candidate, reads the candidate's bit from the bitmap, and runs
+//     Baillie-PSW on the first survivor; a lane whose even is settled claims
+//     the next unclaimed even of the chunk (one atomic per wave and round), so
+//     every lane stays busy until the chunk runs out.
+// Survivors of the sieve to S are prime with probability about 0.9 near 2^64,
+// so an even costs about one Baillie-PSW test.  Evens that no candidate
+// p <= P_max resolves are spilled to the wide Phase-2 kernel, which continues
+// with the table primes above P_max.
 #include "gb_wide.h"
 
 namespace {
-
-constexpr uint32_t kE = 1u << kWideLog2E;
-// window words: E evens plus the halo (at most 32768 bits) and one spare word
-constexpr uint32_t kWideWords = (kE + 32768) / 32 + 2;
 
 __device__ __forceinline__ void max_merge_w(uint64_t &bp, u128w &bn, uint64_t p, u128w n)
 {
@@ -29,139 +35,163 @@ __device__ __forceinline__ void max_merge_w(uint64_t &bp, u128w &bn, uint64_t p,
     }
 }
 
-__global__ __launch_bounds__(kWideThreads) void wide_sieve_probe_kernel(GbWideArgs a)
+// The first bit b >= 0 with q0 + 2b = 0 (mod p), q0 odd, p an odd prime:
+// 2b = -q0 (mod p), so b = x / 2 mod p for x = -q0 mod p.
+__device__ __forceinline__ uint32_t wide_first_bit(u128w q0, uint32_t p)
+{
+    const uint32_t r = w_mod_u32(q0, p);
+    const uint32_t x = r ? p - r : 0u;
+    return (x & 1) ? (x >> 1) + (p >> 1) + 1 : (x >> 1);
+}
+
+// Strikes of the primes below 2^16, one 2^15-bit pass of the chunk's bitmap
+// per workgroup iteration, written out as whole words (every word of the
+// bitmap is written, so nothing needs clearing).  Block 0 also resets the
+// chunk's probe claim counter.
+__global__ __launch_bounds__(256) void wide_small_sieve_kernel(GbWideArgs a, GbWideChunk ch)
+{
+    __shared__ uint32_t w[kWideSieveWords];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (blockIdx.x == 0 && tid == 0)
+        a.ctr[0] = 0;
+    const uint32_t nwords = (ch.nbits + 31) / 32;
+    for (uint32_t w0 = blockIdx.x * kWideSieveWords; w0 < nwords; w0 += gridDim.x * kWideSieveWords) {
+        const uint32_t nw = nwords - w0 < kWideSieveWords ? nwords - w0 : kWideSieveWords;
+        const uint32_t sbits = ch.nbits - 32 * w0 < 32 * nw ? ch.nbits - 32 * w0 : 32 * nw;
+        for (uint32_t x = tid; x < kWideSieveWords; x += 256)
+            w[x] = 0;
+        __syncthreads();
+        const u128w q0 = w_add64(ch.qlo, 64ull * w0);   // odd number of the pass's bit 0
+        for (uint32_t k = 1 + wave; k < a.ncoop; k += 4) {
+            const uint32_t p = a.primes[k];
+            for (uint32_t j = wide_first_bit(q0, p) + lane * p; j < sbits; j += 64 * p)
+                atomicOr(&w[j >> 5], 1u << (j & 31));
+        }
+        for (uint32_t k = a.ncoop + tid; k < a.nsmall; k += 256) {
+            const uint32_t p = a.primes[k];
+            for (uint32_t j = wide_first_bit(q0, p); j < sbits; j += p)
+                atomicOr(&w[j >> 5], 1u << (j & 31));
+        }
+        __syncthreads();
+        for (uint32_t x = tid; x < nw; x += 256)
+            ch.bits[w0 + x] = w[x];
+        __syncthreads();
+    }
+}
+
+// Strikes of the sieving primes from 2^16 to S: one thread per prime, its
+// first multiple in the chunk from one 128-by-32 remainder, then every odd
+// multiple OR-ed into the bitmap.
+__global__ __launch_bounds__(256) void wide_large_fill_kernel(GbWideArgs a, GbWideChunk ch)
+{
+    const uint32_t stride = gridDim.x * 256;
+    for (uint32_t k = a.nsmall + blockIdx.x * 256 + threadIdx.x; k < a.nsieve; k += stride) {
+        const uint32_t p = a.primes[k];
+        for (uint64_t j = wide_first_bit(ch.qlo, p); j < ch.nbits; j += p)
+            atomicOr(&ch.bits[j >> 5], 1u << (j & 31));
+    }
+}
+
+// The probe of one chunk (persistent; the records accumulate over the chunks).
+__global__ __launch_bounds__(kWideThreads) void wide_probe_kernel(GbWideArgs a, GbWideChunk ch)
 {
     constexpr uint32_t NWAVE = kWideThreads / 64;
-    __shared__ uint32_t bits[kWideWords];   // bit b: odd q_lo + 2b has a factor <= S
-    __shared__ unsigned long long sh_seg;
     __shared__ uint64_t red_sum[NWAVE], red_cnt[NWAVE], red_p[NWAVE], red_nl[NWAVE],
         red_nh[NWAVE], red_sp[NWAVE];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t H = a.H;
-
-    for (;;) {
-        if (tid == 0)
-            sh_seg = atomicAdd(&a.ctr[0], 1ull);
-        __syncthreads();
-        const uint64_t seg = sh_seg;
-        if (seg >= a.nsegs)
-            break;
-        const uint64_t rem = a.nE - (uint64_t)kE * seg;
-        const uint32_t cnt = (uint32_t)(rem < kE ? rem : kE);
-        // n0 = A + 2 E seg; q_lo = n0 - 1 - 2H (no wrap: n0 >= 2^64)
-        const u128w n0 = w_add64(a.A, 2ull * kE * seg);
-        const u128w qlo = w_sub64(n0, 1ull + 2ull * H);
-        const uint32_t nbits = cnt + H;          // odd bits [0, nbits) hold every q probed
-        const uint32_t nwords = (nbits + 31) / 32;
-        for (uint32_t w = tid; w < nwords; w += kWideThreads)
-            bits[w] = 0;
-        __syncthreads();
-        // strikes: every odd multiple of each sieving prime in the window
-        // (q_lo + 2j = 0 mod p  <=>  2j = -q_lo mod p)
-        for (uint32_t k = 1 + tid; k < a.nsieve; k += kWideThreads) {
-            const uint32_t p = a.primes[k];
-            const uint32_t r = w_mod_u32(qlo, p);
-            const uint32_t x = r ? p - r : 0u;                    // -q_lo mod p
-            uint32_t j = (x & 1) ? (x >> 1) + (p >> 1) + 1 : (x >> 1);   // x / 2 mod p
-            for (; j < nbits; j += p)
-                atomicOr(&bits[j >> 5], 1u << (j & 31));
-        }
-        __syncthreads();
-
-        // probe: each wave takes a contiguous share of the segment's evens;
-        // a lane holds one even (index i) and its next candidate k, and takes
-        // the next even of the share when its current one is settled
-        const uint32_t share = (cnt + NWAVE - 1) / NWAVE;
-        const uint32_t i0 = wave * share;
-        const uint32_t i1 = i0 + share < cnt ? i0 + share : cnt;
-        uint64_t sum = 0, nres = 0, bp = 0, nsp = 0;
-        u128w bn = {0, 0};
-        uint32_t next = i0 + 64;    // first even of the share not yet handed out
-        uint32_t i = i0 + lane;
-        uint32_t k = 1;
-        bool active = i < i1;
-        while (__ballot(active) != 0) {
-            bool settled = false;
-            if (active) {
-                // next surviving candidate: bit(n - p) = i + H - (p - 1)/2 clear
-                uint32_t p = 0;
-                for (; k <= a.ncand; ++k) {
-                    p = a.primes[k];
-                    const uint32_t b = i + H - (p >> 1);
-                    if (((bits[b >> 5] >> (b & 31)) & 1u) == 0)
-                        break;
-                }
-                const u128w n = w_add64(n0, 2ull * i);
-                if (k > a.ncand) {
-                    // no candidate p <= P_max: to Phase 2
-                    const unsigned long long e = atomicAdd(&a.ctr[1], 1ull);
-                    if (e < a.spill_cap) {
-                        a.spill[e].n_lo = n.lo;
-                        a.spill[e].n_hi = n.hi;
-                        a.spill[e].p = 0;
-                    }
-                    ++nsp;
-                    settled = true;
-                } else if (w_bpsw(w_sub64(n, p))) {
-                    sum += p;
-                    ++nres;
-                    max_merge_w(bp, bn, p, n);
-                    settled = true;
-                } else {
-                    ++k;
-                }
+    const uint32_t *bits = ch.bits;
+    uint64_t sum = 0, nres = 0, bp = 0, nsp = 0;
+    u128w bn = {0, 0};
+    uint64_t claim = 0;
+    if (lane == 0)
+        claim = atomicAdd(&a.ctr[0], 64ull);
+    claim = __shfl(claim, 0, 64);
+    uint64_t i = claim + lane;
+    uint32_t k = 1;
+    bool active = i < ch.cnt;
+    while (__ballot(active) != 0) {
+        bool settled = false;
+        if (active) {
+            // next surviving candidate: bit(n - p) = i + H - (p - 1)/2 clear
+            uint32_t p = 0;
+            for (; k <= a.ncand; ++k) {
+                p = a.primes[k];
+                const uint32_t b = (uint32_t)i + H - (p >> 1);
+                if (((bits[b >> 5] >> (b & 31)) & 1u) == 0)
+                    break;
             }
-            // settled lanes take the next evens of the share, in lane order
-            const unsigned long long need = __ballot(active && settled);
+            const u128w n = w_add64(ch.n0, 2ull * i);
+            if (k > a.ncand) {
+                // no candidate p <= P_max: to Phase 2
+                const unsigned long long e = atomicAdd(&a.ctr[1], 1ull);
+                if (e < a.spill_cap) {
+                    a.spill[e].n_lo = n.lo;
+                    a.spill[e].n_hi = n.hi;
+                    a.spill[e].p = 0;
+                }
+                ++nsp;
+                settled = true;
+            } else if (w_bpsw(w_sub64(n, p))) {
+                sum += p;
+                ++nres;
+                max_merge_w(bp, bn, p, n);
+                settled = true;
+            } else {
+                ++k;
+            }
+        }
+        // settled lanes claim the next evens of the chunk, in lane order
+        const unsigned long long need = __ballot(active && settled);
+        if (need) {
+            uint64_t base = 0;
+            if (lane == 0)
+                base = atomicAdd(&a.ctr[0], (unsigned long long)__popcll(need));
+            base = __shfl(base, 0, 64);
             if (active && settled) {
-                const uint32_t rank = (uint32_t)__popcll(need & ((1ull << lane) - 1));
-                i = next + rank;
+                i = base + (uint64_t)__popcll(need & ((1ull << lane) - 1));
                 k = 1;
-                active = i < i1;
+                active = i < ch.cnt;
             }
-            next += (uint32_t)__popcll(need);
         }
-        // workgroup reduction of the segment's aggregates
+    }
+    // workgroup reduction, merged into this block's record
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            sum += __shfl_xor(sum, off, 64);
-            nres += __shfl_xor(nres, off, 64);
-            nsp += __shfl_xor(nsp, off, 64);
-            const uint64_t op = __shfl_xor(bp, off, 64);
-            u128w on;
-            on.lo = __shfl_xor(bn.lo, off, 64);
-            on.hi = __shfl_xor(bn.hi, off, 64);
-            if (op)
-                max_merge_w(bp, bn, op, on);
+    for (int off = 32; off > 0; off >>= 1) {
+        sum += __shfl_xor(sum, off, 64);
+        nres += __shfl_xor(nres, off, 64);
+        nsp += __shfl_xor(nsp, off, 64);
+        const uint64_t op = __shfl_xor(bp, off, 64);
+        u128w on;
+        on.lo = __shfl_xor(bn.lo, off, 64);
+        on.hi = __shfl_xor(bn.hi, off, 64);
+        if (op)
+            max_merge_w(bp, bn, op, on);
+    }
+    if (lane == 0) {
+        red_sum[wave] = sum;
+        red_cnt[wave] = nres;
+        red_p[wave] = bp;
+        red_nl[wave] = bn.lo;
+        red_nh[wave] = bn.hi;
+        red_sp[wave] = nsp;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        GbWideRecord r = a.rec[blockIdx.x];
+        u128w n = {r.max_n_lo, r.max_n_hi};
+        uint64_t p = r.max_p;
+        for (uint32_t w = 0; w < NWAVE; ++w) {
+            r.checksum += red_sum[w];
+            r.verified += red_cnt[w];
+            r.nspill += red_sp[w];
+            if (red_p[w])
+                max_merge_w(p, n, red_p[w], u128w{red_nl[w], red_nh[w]});
         }
-        if (lane == 0) {
-            red_sum[wave] = sum;
-            red_cnt[wave] = nres;
-            red_p[wave] = bp;
-            red_nl[wave] = bn.lo;
-            red_nh[wave] = bn.hi;
-            red_sp[wave] = nsp;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            GbWideRecord r = {};
-            u128w n = {0, 0};
-            uint64_t p = 0;
-            for (uint32_t w = 0; w < NWAVE; ++w) {
-                r.checksum += red_sum[w];
-                r.verified += red_cnt[w];
-                r.nspill += red_sp[w];
-                if (red_p[w])
-                    max_merge_w(p, n, red_p[w], u128w{red_nl[w], red_nh[w]});
-            }
-            r.max_p = p;
-            r.max_n_lo = n.lo;
-            r.max_n_hi = n.hi;
-            a.rec[seg] = r;
-        }
-        // the next claim is published by the barrier at the top of the loop,
-        // after which the window is cleared: every wave is past its probe here
-        __syncthreads();
+        r.max_p = p;
+        r.max_n_lo = n.lo;
+        r.max_n_hi = n.hi;
+        a.rec[blockIdx.x] = r;
     }
 }
 
@@ -207,7 +237,7 @@ __global__ __launch_bounds__(256) void wide_phase2_kernel(GbWideArgs a)
     }
 }
 
-// One workgroup: fold the segment records and the Phase-2 results, and write
+// One workgroup: fold the probe records and the Phase-2 results, and write
 // the unresolved evens (p = 0 or p > P_max) in ascending order by counting
 // rank (the spill list holds at most 2^16 entries on this path).
 __global__ __launch_bounds__(256) void wide_reduce_kernel(GbWideArgs a, uint64_t P_max,
@@ -217,7 +247,7 @@ __global__ __launch_bounds__(256) void wide_reduce_kernel(GbWideArgs a, uint64_t
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint64_t s = 0, c = 0, bp = 0, failed = 0, un = 0;
     u128w bn = {0, 0};
-    for (uint64_t g = tid; g < a.nsegs; g += 256) {
+    for (uint64_t g = tid; g < a.nrec; g += 256) {
         const GbWideRecord r = a.rec[g];
         s += r.checksum;
         c += r.verified;
@@ -291,10 +321,13 @@ __global__ __launch_bounds__(256) void wide_reduce_kernel(GbWideArgs a, uint64_t
     }
 }
 
-__global__ void wide_reset_kernel(unsigned long long *ctr)
+__global__ __launch_bounds__(256) void wide_reset_kernel(GbWideArgs a)
 {
-    if (threadIdx.x < 2)
-        ctr[threadIdx.x] = 0;
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t < 2)
+        a.ctr[t] = 0;
+    if (t < a.nrec)
+        a.rec[t] = GbWideRecord{};
 }
 
 __global__ __launch_bounds__(256) void bpsw_kernel(const u128w *q, uint64_t count, uint8_t *out)
@@ -316,17 +349,28 @@ __global__ __launch_bounds__(256) void bpsw_kernel(const u128w *q, uint64_t coun
 
 }  // namespace
 
-hipError_t gb_launch_wide(const GbWideArgs &a, uint32_t grid, hipStream_t s)
+hipError_t gb_launch_wide_chunk(const GbWideArgs &a, const GbWideChunk &ch, uint32_t sieve_grid,
+                                uint32_t fill_grid, uint32_t grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(wide_sieve_probe_kernel, dim3(grid), dim3(kWideThreads), 0, s, a);
+    hipLaunchKernelGGL(wide_small_sieve_kernel, dim3(sieve_grid), dim3(256), 0, s, a, ch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    if (fill_grid) {
+        hipLaunchKernelGGL(wide_large_fill_kernel, dim3(fill_grid), dim3(256), 0, s, a, ch);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(wide_probe_kernel, dim3(grid), dim3(kWideThreads), 0, s, a, ch);
     return hipGetLastError();
 }
 
 int gb_wide_occupancy()
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wide_sieve_probe_kernel, kWideThreads,
-                                                     0) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wide_probe_kernel, kWideThreads, 0) !=
+        hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }
@@ -346,9 +390,10 @@ hipError_t gb_launch_wide_reduce(const GbWideArgs &a, uint64_t P_max, GbWideResu
     return hipGetLastError();
 }
 
-hipError_t gb_launch_wide_reset(unsigned long long *ctr, hipStream_t s)
+hipError_t gb_launch_wide_reset(const GbWideArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(wide_reset_kernel, dim3(1), dim3(64), 0, s, ctr);
+    const uint32_t n = a.nrec > 2 ? a.nrec : 2;
+    hipLaunchKernelGGL(wide_reset_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -71,6 +71,18 @@ def test_host_validation_of_params(gb):
     assert gb.get_params() == saved
 
 
+def test_host_validation_of_wide_chunk(gb):
+    assert gb.get_wide_chunk_log2() == 26
+    for bad in (0, 11, 31, 64):
+        with pytest.raises(gb.GoldbachError) as e:
+            gb.set_wide_chunk_log2(bad)
+        assert e.value.name == "GB_EINVAL"
+        assert gb.get_wide_chunk_log2() == 26
+    for ok in (12, 30, 26):
+        gb.set_wide_chunk_log2(ok)
+        assert gb.get_wide_chunk_log2() == ok
+
+
 def test_base_primes_rejects_limit_above_2_32(gb):
     with pytest.raises(gb.GoldbachError) as e:
         gb.base_primes(1 << 32)

@@ -2,7 +2,7 @@
 C ABI against the wide CPU oracle (oracle/gb_oracle_wide.c), field by field,
 bit-exact: windows just above 2^64, at 2^80, 2^100, 2^127 and at the top of
 the u128 range, a range straddling 2^64 (the part below goes through the
-64-bit path), a multi-segment range with a ragged tail, tiny P_max with
+64-bit path), one range cut into chunks of three sizes with ragged tails, tiny P_max with
 Phase 2 and unresolved lists, normalization and refusals."""
 import concurrent.futures as cf
 import random
@@ -108,15 +108,23 @@ def test_straddles_2_64(gb, O):
         assert low[f] == lo[f]
 
 
-def test_multi_segment_ragged(gb, O):
-    """Two full segments of 2^16 evens and a ragged third."""
+def test_chunks_ragged(gb, O):
+    """One range in one chunk (the default 2^26 evens), in chunks of 2^16 (two
+    full and a ragged third) and of 2^12 (34, the last ragged): every split
+    gives the oracle's result."""
     A = 2**64 + 2 * 10**9
     B = A + 2 * (2 * 65536 + 4321 - 1)
-    print("[gpu-wide] multi-segment range", flush=True)
-    g = gb.verify_range_u128(A, B, 65536)
     o = oracle_split(O, A, B, 65536, 10**7)
-    same(g, o, "multi-segment")
-    assert gb.last_stats()["segments"] == 3
+    assert gb.get_wide_chunk_log2() == 26
+    try:
+        for lg, chunks in ((26, 1), (16, 3), (12, 34)):
+            print("[gpu-wide] chunks of 2^%d evens" % lg, flush=True)
+            gb.set_wide_chunk_log2(lg)
+            g = gb.verify_range_u128(A, B, 65536)
+            same(g, o, "chunks of 2^%d" % lg)
+            assert gb.last_stats()["segments"] == chunks
+    finally:
+        gb.set_wide_chunk_log2(26)
 
 
 @pytest.mark.parametrize("P", [7, 31, 1000])
