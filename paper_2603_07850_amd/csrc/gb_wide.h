@@ -4,7 +4,7 @@
 // Montgomery multiplication modulo an odd 128-bit q (R = 2^128) and the
 // Baillie-PSW probable-prime test (strong test to base 2, then the strong
 // Lucas test with Selfridge's parameters D = 5, -7, 9, ...; P = 1,
-// Q = (1 - D)/4).
+// Q = (1 - D)/4, evaluated on the V sequence alone).
 #pragma once
 
 #include "gb_arith.h"
@@ -78,63 +78,51 @@ __device__ __forceinline__ u128w w_submod(u128w a, u128w b, u128w q)
     return r;
 }
 
-// x / 2 mod q for odd q.
-__device__ __forceinline__ u128w w_half(u128w x, u128w q)
+// Montgomery product a * b * 2^-128 mod q for odd q and a, b < q: word-serial
+// reduction over four 32-bit limbs (each limb product with its addends fits
+// one 32x32+64-bit multiply-add, which issues at the full VALU rate);
+// qinv = -q^-1 mod 2^64, of which the low 32 bits serve.  The running value
+// stays below 2q, so a fifth limb holds its top bit.
+__device__ __forceinline__ u128w w_mont_mul(u128w A, u128w B, u128w Q, uint64_t qinv)
 {
-    const bool odd = (x.lo & 1) != 0;
-    u128w r;
-    r.lo = (x.lo >> 1) | (x.hi << 63);
-    r.hi = x.hi >> 1;
-    if (odd) {
-        // (x + q) / 2 = x/2 + q/2 + 1 for odd x and q (floors), without overflow
-        u128w h;
-        h.lo = (q.lo >> 1) | (q.hi << 63);
-        h.hi = q.hi >> 1;
-        r.lo += h.lo;
-        r.hi += h.hi + (r.lo < h.lo ? 1u : 0u);
-        r = w_add64(r, 1);
-    }
-    return r;
-}
-
-// a * b + c + d as (hi, lo); cannot overflow 128 bits.
-__device__ __forceinline__ void mac64(uint64_t a, uint64_t b, uint64_t c, uint64_t d,
-                                      uint64_t &lo, uint64_t &hi)
-{
-    uint64_t l = a * b;
-    uint64_t h = __umul64hi(a, b);
-    l += c;
-    h += l < c ? 1u : 0u;
-    l += d;
-    h += l < d ? 1u : 0u;
-    lo = l;
-    hi = h;
-}
-
-// Montgomery product a * b * 2^-128 mod q for odd q and a, b < q, by
-// word-serial reduction (two 64-bit words); qinv = -q^-1 mod 2^64.  The
-// running value stays below 2q, so a third word holds its top bit.
-__device__ __forceinline__ u128w w_mont_mul(u128w a, u128w b, u128w q, uint64_t qinv)
-{
-    uint64_t t0 = 0, t1 = 0, t2 = 0;
+    const uint32_t a[4] = {(uint32_t)A.lo, (uint32_t)(A.lo >> 32), (uint32_t)A.hi,
+                           (uint32_t)(A.hi >> 32)};
+    const uint32_t b[4] = {(uint32_t)B.lo, (uint32_t)(B.lo >> 32), (uint32_t)B.hi,
+                           (uint32_t)(B.hi >> 32)};
+    const uint32_t q[4] = {(uint32_t)Q.lo, (uint32_t)(Q.lo >> 32), (uint32_t)Q.hi,
+                           (uint32_t)(Q.hi >> 32)};
+    const uint32_t qi = (uint32_t)qinv;
+    uint32_t t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const uint64_t bi = i == 0 ? b.lo : b.hi;
-        uint64_t c, t3;
-        mac64(a.lo, bi, t0, 0, t0, c);
-        mac64(a.hi, bi, t1, c, t1, c);
-        t2 += c;
-        t3 = t2 < c ? 1u : 0u;
-        const uint64_t m = t0 * qinv;
-        uint64_t dummy;
-        mac64(m, q.lo, t0, 0, dummy, c);   // low word becomes zero
-        mac64(m, q.hi, t1, c, t0, c);
-        t1 = t2 + c;
-        t2 = t3 + (t1 < c ? 1u : 0u);
+    for (int i = 0; i < 4; ++i) {
+        // t += a * b[i] (six limbs)
+        uint64_t uv = (uint64_t)a[0] * b[i] + t0;
+        t0 = (uint32_t)uv;
+        uv = (uint64_t)a[1] * b[i] + t1 + (uv >> 32);
+        t1 = (uint32_t)uv;
+        uv = (uint64_t)a[2] * b[i] + t2 + (uv >> 32);
+        t2 = (uint32_t)uv;
+        uv = (uint64_t)a[3] * b[i] + t3 + (uv >> 32);
+        t3 = (uint32_t)uv;
+        uv = (uint64_t)t4 + (uv >> 32);
+        t4 = (uint32_t)uv;
+        const uint32_t t5 = (uint32_t)(uv >> 32);
+        // t = (t + m q) / 2^32 with m making the low limb zero
+        const uint32_t m = t0 * qi;
+        uv = (uint64_t)m * q[0] + t0;
+        uv = (uint64_t)m * q[1] + t1 + (uv >> 32);
+        t0 = (uint32_t)uv;
+        uv = (uint64_t)m * q[2] + t2 + (uv >> 32);
+        t1 = (uint32_t)uv;
+        uv = (uint64_t)m * q[3] + t3 + (uv >> 32);
+        t2 = (uint32_t)uv;
+        uv = (uint64_t)t4 + (uv >> 32);
+        t3 = (uint32_t)uv;
+        t4 = t5 + (uint32_t)(uv >> 32);
     }
-    u128w r = {t0, t1};
-    if (t2 != 0 || !w_lt(r, q))
-        r = w_sub(r, q);
+    u128w r = {((uint64_t)t1 << 32) | t0, ((uint64_t)t3 << 32) | t2};
+    if (t4 != 0 || !w_lt(r, Q))
+        r = w_sub(r, Q);
     return r;
 }
 
@@ -148,11 +136,13 @@ __device__ __forceinline__ uint64_t w_qinv(uint64_t q0)
     return 0 - inv;
 }
 
-// 2^k mod q for q > 2^64 (so 1 < q), by k modular doublings of 1.
-__device__ __forceinline__ u128w w_pow2_mod(int k, u128w q)
+// 2^128 mod q for odd q > 1: from 2^(L-1) < q (L the bit length of q), by
+// 129 - L modular doublings.
+__device__ __forceinline__ u128w w_r_mod(u128w q)
 {
-    u128w x = {1, 0};
-    for (int i = 0; i < k; ++i)
+    const int L = q.hi ? 128 - __builtin_clzll(q.hi) : 64 - __builtin_clzll(q.lo);
+    u128w x = L > 64 ? u128w{0, 1ull << (L - 65)} : u128w{1ull << (L - 1), 0};
+    for (int i = L - 1; i < 128; ++i)
         x = w_addmod(x, x, q);
     return x;
 }
@@ -232,7 +222,7 @@ __device__ inline bool w_is_square(u128w q)
 __device__ inline bool w_bpsw(u128w q)
 {
     const uint64_t qinv = w_qinv(q.lo);
-    const u128w one = w_pow2_mod(128, q);   // R mod q: Montgomery form of 1
+    const u128w one = w_r_mod(q);   // R mod q: Montgomery form of 1
     const u128w minus_one = w_sub(q, one);
     // strong probable prime to base 2: q - 1 = d * 2^s
     u128w d = w_sub64(q, 1);
@@ -277,10 +267,7 @@ __device__ inline bool w_bpsw(u128w q)
         D = D > 0 ? -(D + 2) : -D + 2;
     }
     const int32_t Qs = (1 - D) / 4;
-    // Montgomery forms of D and Q
-    u128w Dm = w_small_mul((uint32_t)(D < 0 ? -D : D), one, q);
-    if (D < 0)
-        Dm = w_sub(q, Dm);
+    // Montgomery form of Q
     u128w Qm = w_small_mul((uint32_t)(Qs < 0 ? -Qs : Qs), one, q);
     if (Qs < 0 && !w_zero(Qm))
         Qm = w_sub(q, Qm);
@@ -292,23 +279,30 @@ __device__ inline bool w_bpsw(u128w q)
         d.hi >>= 1;
         ++s;
     }
+    // The ladder keeps (V_k, V_k+1, Q^k) and doubles k, adding one where the
+    // bit of d is set:
+    //   V_2k = V_k^2 - 2 Q^k,  V_2k+1 = V_k V_k+1 - P Q^k,  V_2k+2 = V_k+1^2 - 2 Q^k+1.
+    // U is not carried: D U_k = 2 V_k+1 - P V_k, and D is a unit mod q
+    // ((D / q) = -1), so U_d = 0 (mod q) exactly when 2 V_d+1 = P V_d.  Every
+    // step is the same four products whatever the bit (no divergence).
     const int top = d.hi ? 127 - __builtin_clzll(d.hi) : 63 - __builtin_clzll(d.lo);
-    u128w U = one, V = one, Qk = Qm;   // U_1 = 1, V_1 = P = 1
+    u128w V = one;                                      // V_1 = P = 1
+    u128w V1 = w_submod(one, w_addmod(Qm, Qm, q), q);   // V_2 = P^2 - 2Q
+    u128w Qk = Qm;                                      // Q^1
     for (int i = top - 1; i >= 0; --i) {
-        U = w_mont_mul(U, V, q, qinv);
-        V = w_submod(w_mont_mul(V, V, q, qinv), w_addmod(Qk, Qk, q), q);
-        Qk = w_mont_mul(Qk, Qk, q, qinv);
         const uint64_t w = i >= 64 ? d.hi : d.lo;
-        if ((w >> (i & 63)) & 1) {
-            const u128w U2 = w_half(w_addmod(U, V, q), q);
-            const u128w V2 = w_half(w_addmod(w_mont_mul(Dm, U, q, qinv), V, q), q);
-            U = U2;
-            V = V2;
-            Qk = w_mont_mul(Qk, Qm, q, qinv);
-        }
+        const bool bit = ((w >> (i & 63)) & 1) != 0;
+        const u128w QkQ = w_mont_mul(Qk, Qm, q, qinv);
+        const u128w Qb = bit ? QkQ : Qk;                // Q^(k + bit)
+        const u128w x = bit ? V1 : V;
+        const u128w prod = w_submod(w_mont_mul(V, V1, q, qinv), Qk, q);
+        const u128w sq = w_submod(w_mont_mul(x, x, q, qinv), w_addmod(Qb, Qb, q), q);
+        V = bit ? prod : sq;
+        V1 = bit ? sq : prod;
+        Qk = w_mont_mul(Qk, Qb, q, qinv);               // Q^(2k + bit)
     }
-    if (w_zero(U) || w_zero(V))
-        return true;
+    if (w_eq(w_addmod(V1, V1, q), V) || w_zero(V))
+        return true;   // U_d = 0 or V_d = 0
     for (int r = 1; r < s; ++r) {
         V = w_submod(w_mont_mul(V, V, q, qinv), w_addmod(Qk, Qk, q), q);
         Qk = w_mont_mul(Qk, Qk, q, qinv);
