@@ -203,6 +203,7 @@ struct GbWideChunk {
     uint32_t cnt;
     uint32_t nbits;
     uint32_t *bits;       // ceil(nbits / 32) words; bit b set: q_lo + 2b has a factor <= S
+    uint32_t lucas_at;    // a wave runs its Lucas round once this many lanes are ready
 };
 
 constexpr int kWideThreads = 256;

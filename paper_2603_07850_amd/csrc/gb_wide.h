@@ -217,12 +217,12 @@ __device__ inline bool w_is_square(u128w q)
     return w_eq(sq, q);
 }
 
-// Baillie-PSW probable-prime test of an odd q > 2^64 that has no prime
-// factor up to 97 (the sieve has removed every factor up to its bound).
-__device__ inline bool w_bpsw(u128w q)
+// The two halves of the Baillie-PSW test of an odd q > 2^64 that has no prime
+// factor up to 97 (the sieve has removed every factor up to its bound), with
+// qinv = w_qinv(q.lo) and one = w_r_mod(q).  First the strong probable-prime
+// test to base 2:
+__device__ inline bool w_sprp2(u128w q, uint64_t qinv, u128w one)
 {
-    const uint64_t qinv = w_qinv(q.lo);
-    const u128w one = w_r_mod(q);   // R mod q: Montgomery form of 1
     const u128w minus_one = w_sub(q, one);
     // strong probable prime to base 2: q - 1 = d * 2^s
     u128w d = w_sub64(q, 1);
@@ -232,23 +232,25 @@ __device__ inline bool w_bpsw(u128w q)
         d.hi >>= 1;
         ++s;
     }
-    {
-        const int top = d.hi ? 127 - __builtin_clzll(d.hi) : 63 - __builtin_clzll(d.lo);
-        u128w x = one;
-        for (int i = top; i >= 0; --i) {
-            x = w_mont_mul(x, x, q, qinv);
-            const uint64_t w = i >= 64 ? d.hi : d.lo;
-            if ((w >> (i & 63)) & 1)
-                x = w_addmod(x, x, q);   // times the base 2
-        }
-        bool pass = w_eq(x, one) || w_eq(x, minus_one);
-        for (int r = 1; r < s && !pass; ++r) {
-            x = w_mont_mul(x, x, q, qinv);
-            pass = w_eq(x, minus_one);
-        }
-        if (!pass)
-            return false;
+    const int top = d.hi ? 127 - __builtin_clzll(d.hi) : 63 - __builtin_clzll(d.lo);
+    u128w x = one;
+    for (int i = top; i >= 0; --i) {
+        x = w_mont_mul(x, x, q, qinv);
+        const uint64_t w = i >= 64 ? d.hi : d.lo;
+        if ((w >> (i & 63)) & 1)
+            x = w_addmod(x, x, q);   // times the base 2
     }
+    bool pass = w_eq(x, one) || w_eq(x, minus_one);
+    for (int r = 1; r < s && !pass; ++r) {
+        x = w_mont_mul(x, x, q, qinv);
+        pass = w_eq(x, minus_one);
+    }
+    return pass;
+}
+
+// then the strong Lucas test with Selfridge's parameters.
+__device__ inline bool w_slucas(u128w q, uint64_t qinv, u128w one)
+{
     // Selfridge: the first D of 5, -7, 9, -11, ... with (D / q) = -1
     int32_t D = 5;
     int tries = 0;
@@ -272,8 +274,8 @@ __device__ inline bool w_bpsw(u128w q)
     if (Qs < 0 && !w_zero(Qm))
         Qm = w_sub(q, Qm);
     // q + 1 = d * 2^s (q + 1 cannot wrap: q < 2^128 - 1)
-    d = w_add64(q, 1);
-    s = 0;
+    u128w d = w_add64(q, 1);
+    int s = 0;
     while ((d.lo & 1) == 0) {
         d.lo = (d.lo >> 1) | (d.hi << 63);
         d.hi >>= 1;
@@ -310,4 +312,12 @@ __device__ inline bool w_bpsw(u128w q)
             return true;
     }
     return false;
+}
+
+// Baillie-PSW: both halves.
+__device__ inline bool w_bpsw(u128w q)
+{
+    const uint64_t qinv = w_qinv(q.lo);
+    const u128w one = w_r_mod(q);   // R mod q: Montgomery form of 1
+    return w_sprp2(q, qinv, one) && w_slucas(q, qinv, one);
 }

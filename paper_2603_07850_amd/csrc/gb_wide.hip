@@ -16,7 +16,9 @@
 //     bitmap with device atomics (a few per thousand bits each);
 //   * a persistent probe over all CUs: a lane holds one even and its next
 //     candidate, reads the candidate's bit from the bitmap, and runs
-//     Baillie-PSW on the first survivor; a lane whose even is settled claims
+//     Baillie-PSW on the first survivor (the base-2 test and the Lucas test in
+//     rounds of their own, so that lanes whose survivor fails the base-2 test
+//     do not wait through a Lucas test); a lane whose even is settled claims
 //     the next unclaimed even of the chunk (one atomic per wave and round), so
 //     every lane stays busy until the chunk runs out.
 // Survivors of the sieve to S are prime with probability about 0.9 near 2^64,
@@ -110,29 +112,58 @@ __global__ __launch_bounds__(kWideThreads) void wide_probe_kernel(GbWideArgs a, 
     uint64_t i = claim + lane;
     uint32_t k = 1;
     bool active = i < ch.cnt;
-    while (__ballot(active) != 0) {
+    // A lane is `ready` when its candidate primes[k] has passed the base-2
+    // test (qinv and one kept for the Lucas test).  A wave runs base-2 rounds,
+    // in which every lane without a ready candidate scans to its next survivor
+    // and tests it, until lucas_at of its active lanes are ready, then one
+    // Lucas round for the ready lanes: the base-2 failures (most composite
+    // survivors) then cost a base-2 test, not a whole Baillie-PSW round.
+    bool ready = false;
+    uint64_t qinv = 0;
+    u128w one = {0, 0};
+    for (;;) {
+        const unsigned long long act = __ballot(active);
+        if (act == 0)
+            break;
+        const uint32_t nact = (uint32_t)__popcll(act);
+        const uint32_t nrdy = (uint32_t)__popcll(__ballot(active && ready));
         bool settled = false;
-        if (active) {
-            // next surviving candidate: bit(n - p) = i + H - (p - 1)/2 clear
-            uint32_t p = 0;
-            for (; k <= a.ncand; ++k) {
-                p = a.primes[k];
-                const uint32_t b = (uint32_t)i + H - (p >> 1);
-                if (((bits[b >> 5] >> (b & 31)) & 1u) == 0)
-                    break;
-            }
-            const u128w n = w_add64(ch.n0, 2ull * i);
-            if (k > a.ncand) {
-                // no candidate p <= P_max: to Phase 2
-                const unsigned long long e = atomicAdd(&a.ctr[1], 1ull);
-                if (e < a.spill_cap) {
-                    a.spill[e].n_lo = n.lo;
-                    a.spill[e].n_hi = n.hi;
-                    a.spill[e].p = 0;
+        if (nrdy < (nact < ch.lucas_at ? nact : ch.lucas_at)) {
+            if (active && !ready) {
+                // next surviving candidate: bit(n - p) = i + H - (p - 1)/2 clear
+                uint32_t p = 0;
+                for (; k <= a.ncand; ++k) {
+                    p = a.primes[k];
+                    const uint32_t b = (uint32_t)i + H - (p >> 1);
+                    if (((bits[b >> 5] >> (b & 31)) & 1u) == 0)
+                        break;
                 }
-                ++nsp;
-                settled = true;
-            } else if (w_bpsw(w_sub64(n, p))) {
+                const u128w n = w_add64(ch.n0, 2ull * i);
+                if (k > a.ncand) {
+                    // no candidate p <= P_max: to Phase 2
+                    const unsigned long long e = atomicAdd(&a.ctr[1], 1ull);
+                    if (e < a.spill_cap) {
+                        a.spill[e].n_lo = n.lo;
+                        a.spill[e].n_hi = n.hi;
+                        a.spill[e].p = 0;
+                    }
+                    ++nsp;
+                    settled = true;
+                } else {
+                    const u128w q = w_sub64(n, p);
+                    qinv = w_qinv(q.lo);
+                    one = w_r_mod(q);
+                    if (w_sprp2(q, qinv, one))
+                        ready = true;
+                    else
+                        ++k;
+                }
+            }
+        } else if (active && ready) {
+            const uint32_t p = a.primes[k];
+            const u128w n = w_add64(ch.n0, 2ull * i);
+            ready = false;
+            if (w_slucas(w_sub64(n, p), qinv, one)) {
                 sum += p;
                 ++nres;
                 max_merge_w(bp, bn, p, n);
