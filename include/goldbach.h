@@ -200,9 +200,9 @@ gb_status gb_verify_batch(const uint64_t *AB, uint64_t k, uint64_t P_max,
  * Baillie-PSW test (a strong probable-prime test to base 2 and a strong Lucas
  * test with Selfridge's parameters; no composite passing it is known):
  *     p_min(n) = min { p prime : n - p passes Baillie-PSW }.
- * The segment window, sieved in LDS by the table primes up to
- * min(T, 2^28) with 128-bit offsets, only removes q with small factors; the
- * survivors are tested in ascending p.  P_max and Phase 2 as in
+ * The range is taken in chunks (gb_set_wide_chunk_log2); each chunk's strike
+ * bitmap, sieved by the table primes up to min(T, 2^28) with 128-bit offsets,
+ * only removes q with small factors; the survivors are tested in ascending p.  P_max and Phase 2 as in
  * gb_verify_range (Phase 2 tests table primes above P_max by Baillie-PSW).
  *   A, B   any u128 pair (normalized inward to even numbers, A raised to 4;
  *          B = 2^128 - 1 rounds to 2^128 - 2).  At most 2^40 evens at or
@@ -212,7 +212,9 @@ gb_status gb_verify_batch(const uint64_t *AB, uint64_t k, uint64_t P_max,
  *          (lo, hi) halves of each unresolved n in ascending order.
  * Errors as gb_verify_range; GB_ENOMEM when more than 65536 evens at or above
  * 2^64 are left open by P_max (a tiny P_max over a long range).  Blocks until
- * done.  gb_last_stats() describes the wide kernel's launch.
+ * done.  gb_last_stats() describes the part past 2^64: segments = chunks,
+ * seg_log2 = log2 of the chunk size, grid = probe blocks, probe_ms = the
+ * chunks' sieve and probe kernels.
  */
 typedef struct gb_result128 {
     uint64_t A_lo, A_hi, B_lo, B_hi;
