@@ -9,7 +9,10 @@ without blocking the GPU work.  Resources are validated before any work
 anything.
 
 The range is verified in chunks of ``--chunk-evens`` evens, one
-``gb_verify_range`` call each, and the chunk results are merged exactly: the
+``gb_verify_range`` call each (``gb_verify_range_u128`` for a chunk that
+reaches 2^64: past 2^64 primality of n - p is decided by Baillie-PSW, the
+paper's future-work direction of Sec. 5; LIMIT may be up to 2^128 - 1), and
+the chunk results are merged exactly: the
 aggregates of a range are associative over any split into consecutive
 sub-ranges (counts and the checksum add modulo 2^64, the largest minimal p
 keeps the smallest n on ties, unresolved lists concatenate in ascending
@@ -28,13 +31,15 @@ import threading
 import time
 
 U64 = (1 << 64) - 1
+U128 = (1 << 128) - 1
+WIDE_MAX_EVENS = 1 << 40      # evens past 2^64 per library call
 FIELDS = ("verified", "checksum", "max_p", "max_p_n", "n_unresolved", "n_failed")
 
 
 def normalize(A, B):
     """Even bounds [A', B'] of the evens n >= 4 in [A, B]; None if there is none."""
     A = max(4, A + (A & 1))
-    B = min(B, U64 - 1)
+    B = min(B, U128 - 1)
     B -= B & 1
     return (A, B) if A <= B else None
 
@@ -230,8 +235,10 @@ def parse_args(argv):
                  "with --start instead" % a.gpus)
     if a.resume and not a.log:
         ap.error("--resume needs --log")
-    if a.start < 0 or a.limit < 0 or a.limit > U64 or a.start > U64:
-        ap.error("START and LIMIT must be in [0, 2^64 - 1]")
+    if a.start < 0 or a.limit < 0 or a.limit > U128 or a.start > U128:
+        ap.error("START and LIMIT must be in [0, 2^128 - 1]")
+    if a.limit > U64 and a.chunk_evens > WIDE_MAX_EVENS:
+        ap.error("--chunk-evens above 2^40 is not supported past 2^64")
     return a
 
 
@@ -250,14 +257,19 @@ def main(argv=None):
 
 def _main(a, gb):
     nb = normalize(a.start, a.limit)
-    base = a.base_limit or max(math.isqrt(nb[1]) if nb else 0, a.p_max)
+    # past 2^64 the table of primes to 2^32 - 1 serves both parts: the 64-bit
+    # part below 2^64 needs it, and the sieve past 2^64 uses its primes to 2^28
+    wide = nb is not None and nb[1] > U64
+    base = a.base_limit or (U64 >> 32 if wide else
+                            max(math.isqrt(nb[1]) if nb else 0, a.p_max))
     gb.base_primes(base)
     if a.seg_log2:
         gb.set_params(seg_log2=a.seg_log2, wg_size=a.wg_size, window=a.window)
-    elif nb is not None:
-        # tune on a slice of the range's top end (its costliest part)
-        span = min(nb[1] - nb[0], 2 * 10 ** 10)
-        gb.autotune(nb[1] - span, nb[1], a.p_max)
+    elif nb is not None and nb[0] <= U64:
+        # tune on a slice of the 64-bit part's top end (its costliest part)
+        top = min(nb[1], U64 - 1)
+        span = min(top - nb[0], 2 * 10 ** 10)
+        gb.autotune(top - span, top, a.p_max)
 
     total = (nb[1] - nb[0]) // 2 + 1 if nb else 0
     mon = None
@@ -266,6 +278,8 @@ def _main(a, gb):
         mon.start()
 
     def verify(lo, hi, P_max):
+        if hi > U64:
+            return gb.verify_range_u128(lo, hi, P_max, unresolved_cap=a.unresolved_cap)
         return gb.verify_range(lo, hi, P_max, unresolved_cap=a.unresolved_cap)
 
     t0 = time.perf_counter()

@@ -16,6 +16,7 @@ from oracle import oracle as O
 from paper_2603_07850_amd import cli
 
 U64 = (1 << 64) - 1
+U128 = (1 << 128) - 1
 CMP = ("verified", "checksum", "max_p", "max_p_n", "n_unresolved", "n_failed", "unresolved")
 
 
@@ -33,7 +34,8 @@ def same(r, o):
 def test_plan_tiles_the_range():
     rng = random.Random(7)
     cases = [(4, 100, 7), (0, 3, 5), (5, 5, 1), (3, 1001, 1), (10, 8, 3), (4, 4, 100),
-             (U64 - 100, U64, 7), (U64 - 1, U64, 1)]
+             (U64 - 100, U64, 7), (U64 - 1, U64, 1), (U64 - 100, U64 + 100, 13),
+             (U128 - 100, U128, 7), (U128 - 1, U128, 1), (U128, U128, 1)]
     for _ in range(200):
         a = rng.randrange(0, 10 ** 6)
         cases.append((a, a + rng.randrange(0, 10 ** 4), rng.randrange(1, 3000)))
@@ -58,6 +60,9 @@ def test_normalize_edges():
     assert cli.normalize(5, 7) == (6, 6)
     assert cli.normalize(U64, U64) is None
     assert cli.normalize(U64 - 3, U64) == (U64 - 3, U64 - 1)
+    assert cli.normalize(U64, U64 + 1) == (U64 + 1, U64 + 1)
+    assert cli.normalize(U128, U128) is None
+    assert cli.normalize(U128 - 3, U128) == (U128 - 3, U128 - 1)
 
 
 @pytest.mark.parametrize("A,B,P_max,chunk", [(4, 200000, 65536, 9000), (4, 60000, 7, 777),
@@ -67,6 +72,21 @@ def test_merged_chunks_equal_the_whole_range(A, B, P_max, chunk):
     whole = O.verify_range(A, B, P_max, limit)
     res, ran, complete = cli.run(A, B, P_max, chunk, oracle_verify(limit))
     assert complete and ran == len(cli.plan_chunks(A, B, chunk))
+    same(res, whole)
+
+
+def test_merged_chunks_past_2_64():
+    """Chunks on both sides of 2^64 and one across it, against the wide oracle
+    over the whole range."""
+    A, B, P_max, chunk = 2**64 - 2 * 300, 2**64 + 2 * 300, 65536, 137
+
+    def verify(a, b, p):
+        return O.verify_range_wide(a, b, p, 10**6)
+    whole = verify(A, B, P_max)
+    res, ran, complete = cli.run(A, B, P_max, chunk, verify)
+    chunks = cli.plan_chunks(A, B, chunk)
+    assert complete and ran == len(chunks)
+    assert any(a < 2**64 <= b for a, b in chunks)
     same(res, whole)
 
 
@@ -133,7 +153,11 @@ def test_arguments():
         cli.parse_args(["1000", "--gpus", "2"])
     with pytest.raises(SystemExit):
         cli.parse_args(["1000", "--resume"])
+    a = cli.parse_args([str(1 << 64)])                 # past 2^64: Baillie-PSW
+    assert a.limit == 1 << 64
     with pytest.raises(SystemExit):
-        cli.parse_args([str(1 << 64)])
+        cli.parse_args([str(1 << 128)])
+    with pytest.raises(SystemExit):
+        cli.parse_args([str(1 << 70), "--chunk-evens", str((1 << 40) + 1)])
     # the output record is plain JSON
     assert json.loads(json.dumps(cli.empty_result())) == cli.empty_result()

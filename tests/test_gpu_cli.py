@@ -79,3 +79,19 @@ def test_cli_reports_errors():
     print("[gpu] %s" % " ".join(cmd[2:]), flush=True)
     p = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert p.returncode == 2 and "GB_ERANGE" in p.stderr, (p.returncode, p.stderr[-2000:])
+
+
+@pytest.mark.gpu
+def test_cli_past_2_64_matches_wide_oracle():
+    """A range across 2^64 in chunks of 1000 evens (one chunk across 2^64, the
+    rest on either side): the 64-bit path below, Baillie-PSW above, merged;
+    against the wide oracle over the whole range (every even resolves with
+    p <= 2^16, so the oracle's smaller table gives the same result)."""
+    from oracle import oracle as O
+    A, B = 2**64 - 2 * 2500, 2**64 + 2 * 3500
+    rc, out, _ = cli(B, "--start", A, "--chunk-evens", 1000, "--seg-log2", 18, "--wg-size", 256)
+    assert rc == 0 and out["complete"] and out["chunks_run"] == 7
+    o = O.verify_range_wide(A, B, 65536, 10 ** 7)
+    for f in CMP:
+        assert out[f] == o[f], f
+    assert (out["A"], out["B"]) == (A, B)
