@@ -24,6 +24,7 @@
 
 #include "goldbach.h"
 #include "gb_internal.h"
+#include "gb_wide_types.h"
 
 // Scratch of gb_verify_range_noalloc: counters, the interval descriptor and
 // result, the segment records, the spill list and the unresolved list of one

@@ -9,6 +9,7 @@
 
 #include "gb_arith.h"
 #include "gb_internal.h"
+#include "gb_wide_types.h"
 
 __device__ __forceinline__ bool w_lt(u128w a, u128w b)
 {
