@@ -1,15 +1,16 @@
 // gb_wide.h -- 128-bit integer arithmetic of the kernels that verify past
 // 2^64 (Sec. 5, future work: 128-bit sieve arithmetic with a Baillie-PSW
-// test): u128 values as two 64-bit words, remainders by 32-bit primes,
-// Montgomery multiplication modulo an odd 128-bit q (R = 2^128) and the
-// Baillie-PSW probable-prime test (strong test to base 2, then the strong
+// test): u128 values as two 64-bit words, remainders by 32-bit primes, and
+// the Baillie-PSW probable-prime test (strong test to base 2, then the strong
 // Lucas test with Selfridge's parameters D = 5, -7, 9, ...; P = 1,
-// Q = (1 - D)/4, evaluated on the V sequence alone).
+// Q = (1 - D)/4, evaluated on the V sequence alone) over the Montgomery
+// arithmetic of gb_wide_w5.h (R = 2^140).
 #pragma once
 
 #include "gb_arith.h"
 #include "gb_internal.h"
 #include "gb_wide_types.h"
+#include "gb_wide_w5.h"
 
 __device__ __forceinline__ bool w_lt(u128w a, u128w b)
 {
@@ -79,85 +80,57 @@ __device__ __forceinline__ u128w w_submod(u128w a, u128w b, u128w q)
     return r;
 }
 
-// Montgomery product a * b * 2^-128 mod q for odd q and a, b < q: word-serial
-// reduction over four 32-bit limbs (each limb product with its addends fits
-// one 32x32+64-bit multiply-add, which issues at the full VALU rate);
-// qinv = -q^-1 mod 2^64, of which the low 32 bits serve.  The running value
-// stays below 2q, so a fifth limb holds its top bit.
-__device__ __forceinline__ u128w w_mont_mul(u128w A, u128w B, u128w Q, uint64_t qinv)
-{
-    const uint32_t a[4] = {(uint32_t)A.lo, (uint32_t)(A.lo >> 32), (uint32_t)A.hi,
-                           (uint32_t)(A.hi >> 32)};
-    const uint32_t b[4] = {(uint32_t)B.lo, (uint32_t)(B.lo >> 32), (uint32_t)B.hi,
-                           (uint32_t)(B.hi >> 32)};
-    const uint32_t q[4] = {(uint32_t)Q.lo, (uint32_t)(Q.lo >> 32), (uint32_t)Q.hi,
-                           (uint32_t)(Q.hi >> 32)};
-    const uint32_t qi = (uint32_t)qinv;
-    uint32_t t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        // t += a * b[i] (six limbs)
-        uint64_t uv = (uint64_t)a[0] * b[i] + t0;
-        t0 = (uint32_t)uv;
-        uv = (uint64_t)a[1] * b[i] + t1 + (uv >> 32);
-        t1 = (uint32_t)uv;
-        uv = (uint64_t)a[2] * b[i] + t2 + (uv >> 32);
-        t2 = (uint32_t)uv;
-        uv = (uint64_t)a[3] * b[i] + t3 + (uv >> 32);
-        t3 = (uint32_t)uv;
-        uv = (uint64_t)t4 + (uv >> 32);
-        t4 = (uint32_t)uv;
-        const uint32_t t5 = (uint32_t)(uv >> 32);
-        // t = (t + m q) / 2^32 with m making the low limb zero
-        const uint32_t m = t0 * qi;
-        uv = (uint64_t)m * q[0] + t0;
-        uv = (uint64_t)m * q[1] + t1 + (uv >> 32);
-        t0 = (uint32_t)uv;
-        uv = (uint64_t)m * q[2] + t2 + (uv >> 32);
-        t1 = (uint32_t)uv;
-        uv = (uint64_t)m * q[3] + t3 + (uv >> 32);
-        t2 = (uint32_t)uv;
-        uv = (uint64_t)t4 + (uv >> 32);
-        t3 = (uint32_t)uv;
-        t4 = t5 + (uint32_t)(uv >> 32);
-    }
-    u128w r = {((uint64_t)t1 << 32) | t0, ((uint64_t)t3 << 32) | t2};
-    if (t4 != 0 || !w_lt(r, Q))
-        r = w_sub(r, Q);
-    return r;
-}
-
-// -q^-1 mod 2^64 for odd q (Newton steps double the correct low bits).
-__device__ __forceinline__ uint64_t w_qinv(uint64_t q0)
-{
-    uint64_t inv = q0;   // q0 * q0 == 1 (mod 8)
-#pragma unroll
-    for (int i = 0; i < 5; ++i)
-        inv *= 2 - q0 * inv;
-    return 0 - inv;
-}
-
-// 2^128 mod q for odd q > 1: from 2^(L-1) < q (L the bit length of q), by
-// 129 - L modular doublings.
+// 2^140 mod q for odd q > 1 (the Montgomery form of 1): from 2^(L-1) < q (L
+// the bit length of q), by 141 - L modular doublings.
 __device__ __forceinline__ u128w w_r_mod(u128w q)
 {
     const int L = q.hi ? 128 - __builtin_clzll(q.hi) : 64 - __builtin_clzll(q.lo);
     u128w x = L > 64 ? u128w{0, 1ull << (L - 65)} : u128w{1ull << (L - 1), 0};
-    for (int i = L - 1; i < 128; ++i)
+    for (int i = L - 1; i < 140; ++i)
         x = w_addmod(x, x, q);
     return x;
 }
 
-// v * x mod q for a small v < 2^20 and x < q (double and add).
-__device__ __forceinline__ u128w w_small_mul(uint32_t v, u128w x, u128w q)
+// x * c mod q for x < q and 1 <= c < 2^16, q odd with qinv_d = 1 / q in double
+// precision.  The quotient k = floor(x c / q) < 2^16 is estimated in double
+// precision: with at most seven roundings the estimate's relative error is
+// below 2^-50, so its absolute error is below 2^-34 and its floor is k - 1, k
+// or k + 1.  R = x c - k' q is formed over three 64-bit words (its top word is
+// -1, 0 or 1, as R lies in [-q, 2q)) and corrected once either way.
+__device__ __forceinline__ u128w w_mul_small(u128w x, uint32_t c, u128w q, double qinv_d)
 {
-    u128w r = {0, 0};
-    for (int i = 19; i >= 0; --i) {
-        r = w_addmod(r, r, q);
-        if ((v >> i) & 1)
-            r = w_addmod(r, x, q);
+    const double xd = (double)x.hi * 18446744073709551616.0 + (double)x.lo;
+    const double kd = __builtin_floor(xd * (double)c * qinv_d);
+    const uint64_t k = kd > 0.0 ? (uint64_t)kd : 0u;
+    // T = x c and K = k q as (low, middle, top) words
+    const uint64_t tl = x.lo * c;
+    const uint64_t th = __umul64hi(x.lo, (uint64_t)c);
+    const uint64_t tm = x.hi * c + th;
+    const uint64_t tt = __umul64hi(x.hi, (uint64_t)c) + (tm < th ? 1u : 0u);
+    const uint64_t kl = q.lo * k;
+    const uint64_t kh = __umul64hi(q.lo, k);
+    const uint64_t km = q.hi * k + kh;
+    const uint64_t kt = __umul64hi(q.hi, k) + (km < kh ? 1u : 0u);
+    u128w r;
+    r.lo = tl - kl;
+    const uint64_t b0 = tl < kl ? 1u : 0u;
+    r.hi = tm - km - b0;
+    const uint64_t b1 = (tm < km || tm - km < b0) ? 1u : 0u;
+    const uint64_t rt = tt - kt - b1;
+    if ((int64_t)rt < 0) {
+        // R in [-q, 0): R + q, computed modulo 2^128
+        r.lo += q.lo;
+        r.hi += q.hi + (r.lo < q.lo ? 1u : 0u);
+    } else if (rt != 0 || !w_lt(r, q)) {
+        r = w_sub(r, q);   // R in [q, 2q)
     }
     return r;
+}
+
+// Reciprocal of q in double precision.
+__device__ __forceinline__ double w_recip_d(u128w q)
+{
+    return 1.0 / ((double)q.hi * 18446744073709551616.0 + (double)q.lo);
 }
 
 // Jacobi symbol (a / m) for odd 0 < m and 0 <= a < m, 32-bit.
@@ -220,12 +193,14 @@ __device__ inline bool w_is_square(u128w q)
 
 // The two halves of the Baillie-PSW test of an odd q > 2^64 that has no prime
 // factor up to 97 (the sieve has removed every factor up to its bound), with
-// qinv = w_qinv(q.lo) and one = w_r_mod(q).  First the strong probable-prime
+// qi = w5_qinv(q.lo) and one = w_r_mod(q).  First the strong probable-prime
 // test to base 2:
-__device__ inline bool w_sprp2(u128w q, uint64_t qinv, u128w one)
+__device__ inline bool w_sprp2(u128w q, uint32_t qi, u128w one_u)
 {
-    const u128w minus_one = w_sub(q, one);
-    // strong probable prime to base 2: q - 1 = d * 2^s
+    const w5 q5 = w5_from(q.lo, q.hi);
+    const w5 one = w5_from(one_u.lo, one_u.hi);
+    const w5 minus_one = w5_sub(q5, one);
+    // q - 1 = d * 2^s
     u128w d = w_sub64(q, 1);
     int s = 0;
     while ((d.lo & 1) == 0) {
@@ -234,23 +209,24 @@ __device__ inline bool w_sprp2(u128w q, uint64_t qinv, u128w one)
         ++s;
     }
     const int top = d.hi ? 127 - __builtin_clzll(d.hi) : 63 - __builtin_clzll(d.lo);
-    u128w x = one;
+    w5 x = one;
     for (int i = top; i >= 0; --i) {
-        x = w_mont_mul(x, x, q, qinv);
+        x = w5_mont(x, x, q5, qi);                 // below 1.01 q
         const uint64_t w = i >= 64 ? d.hi : d.lo;
         if ((w >> (i & 63)) & 1)
-            x = w_addmod(x, x, q);   // times the base 2
+            x = w5_add(x, x);                      // times the base 2: below 2.02 q
     }
-    bool pass = w_eq(x, one) || w_eq(x, minus_one);
+    x = w5_canon<2>(x, q5);
+    bool pass = w5_eq(x, one) || w5_eq(x, minus_one);
     for (int r = 1; r < s && !pass; ++r) {
-        x = w_mont_mul(x, x, q, qinv);
-        pass = w_eq(x, minus_one);
+        x = w5_canon<1>(w5_mont(x, x, q5, qi), q5);
+        pass = w5_eq(x, minus_one);
     }
     return pass;
 }
 
 // then the strong Lucas test with Selfridge's parameters.
-__device__ inline bool w_slucas(u128w q, uint64_t qinv, u128w one)
+__device__ inline bool w_slucas(u128w q, uint32_t qi, u128w one_u)
 {
     // Selfridge: the first D of 5, -7, 9, -11, ... with (D / q) = -1
     int32_t D = 5;
@@ -270,10 +246,13 @@ __device__ inline bool w_slucas(u128w q, uint64_t qinv, u128w one)
         D = D > 0 ? -(D + 2) : -D + 2;
     }
     const int32_t Qs = (1 - D) / 4;
-    // Montgomery form of Q
-    u128w Qm = w_small_mul((uint32_t)(Qs < 0 ? -Qs : Qs), one, q);
-    if (Qs < 0 && !w_zero(Qm))
-        Qm = w_sub(q, Qm);
+    // 0 < |Q| <= 2^14 + 1 (|D| < 2^16 + 5 by the bound on the search): the
+    // Montgomery forms of Q and of V_2 = P^2 - 2Q come from a small-constant
+    // product and a negation
+    u128w Qm_u = w_mul_small(one_u, (uint32_t)(Qs < 0 ? -Qs : Qs), q, w_recip_d(q));
+    if (Qs < 0 && !w_zero(Qm_u))
+        Qm_u = w_sub(q, Qm_u);
+    const u128w V2_u = w_submod(one_u, w_addmod(Qm_u, Qm_u, q), q);
     // q + 1 = d * 2^s (q + 1 cannot wrap: q < 2^128 - 1)
     u128w d = w_add64(q, 1);
     int s = 0;
@@ -287,29 +266,38 @@ __device__ inline bool w_slucas(u128w q, uint64_t qinv, u128w one)
     //   V_2k = V_k^2 - 2 Q^k,  V_2k+1 = V_k V_k+1 - P Q^k,  V_2k+2 = V_k+1^2 - 2 Q^k+1.
     // U is not carried: D U_k = 2 V_k+1 - P V_k, and D is a unit mod q
     // ((D / q) = -1), so U_d = 0 (mod q) exactly when 2 V_d+1 = P V_d.  Every
-    // step is the same four products whatever the bit (no divergence).
+    // step is the same four Montgomery products whatever the bit (no
+    // divergence); the subtractions are additions of 2q - Q^k and
+    // 2 (2q - Q^(k+bit)), so V_k and V_k+1 stay below 5.01 q unreduced.
+    const w5 q5 = w5_from(q.lo, q.hi);
+    const w5 twoq = w5_norm(w5_add(q5, q5));
+    const w5 Qm = w5_from(Qm_u.lo, Qm_u.hi);
     const int top = d.hi ? 127 - __builtin_clzll(d.hi) : 63 - __builtin_clzll(d.lo);
-    u128w V = one;                                      // V_1 = P = 1
-    u128w V1 = w_submod(one, w_addmod(Qm, Qm, q), q);   // V_2 = P^2 - 2Q
-    u128w Qk = Qm;                                      // Q^1
+    w5 V = w5_from(one_u.lo, one_u.hi);   // V_1 = P = 1
+    w5 V1 = w5_from(V2_u.lo, V2_u.hi);    // V_2
+    w5 Qk = Qm;                           // Q^1
     for (int i = top - 1; i >= 0; --i) {
         const uint64_t w = i >= 64 ? d.hi : d.lo;
         const bool bit = ((w >> (i & 63)) & 1) != 0;
-        const u128w QkQ = w_mont_mul(Qk, Qm, q, qinv);
-        const u128w Qb = bit ? QkQ : Qk;                // Q^(k + bit)
-        const u128w x = bit ? V1 : V;
-        const u128w prod = w_submod(w_mont_mul(V, V1, q, qinv), Qk, q);
-        const u128w sq = w_submod(w_mont_mul(x, x, q, qinv), w_addmod(Qb, Qb, q), q);
+        const w5 QkQ = w5_mont(Qk, Qm, q5, qi);
+        const w5 Qb = bit ? QkQ : Qk;     // Q^(k + bit), below 1.01 q
+        const w5 x = bit ? V1 : V;
+        const w5 prod = w5_add(w5_mont(V, V1, q5, qi), w5_sub(twoq, Qk));
+        const w5 nb = w5_sub(twoq, Qb);
+        const w5 sq = w5_add(w5_mont(x, x, q5, qi), w5_add(nb, nb));
         V = bit ? prod : sq;
         V1 = bit ? sq : prod;
-        Qk = w_mont_mul(Qk, Qb, q, qinv);               // Q^(2k + bit)
+        Qk = w5_mont(Qk, Qb, q5, qi);     // Q^(2k + bit)
     }
-    if (w_eq(w_addmod(V1, V1, q), V) || w_zero(V))
+    V = w5_canon<5>(V, q5);
+    V1 = w5_canon<5>(V1, q5);
+    if (w5_eq(w5_canon<1>(w5_add(V1, V1), q5), V) || w5_zero(V))
         return true;   // U_d = 0 or V_d = 0
     for (int r = 1; r < s; ++r) {
-        V = w_submod(w_mont_mul(V, V, q, qinv), w_addmod(Qk, Qk, q), q);
-        Qk = w_mont_mul(Qk, Qk, q, qinv);
-        if (w_zero(V))
+        const w5 nq = w5_sub(twoq, Qk);
+        V = w5_canon<5>(w5_add(w5_mont(V, V, q5, qi), w5_add(nq, nq)), q5);
+        Qk = w5_mont(Qk, Qk, q5, qi);
+        if (w5_zero(V))
             return true;
     }
     return false;
@@ -318,7 +306,7 @@ __device__ inline bool w_slucas(u128w q, uint64_t qinv, u128w one)
 // Baillie-PSW: both halves.
 __device__ inline bool w_bpsw(u128w q)
 {
-    const uint64_t qinv = w_qinv(q.lo);
-    const u128w one = w_r_mod(q);   // R mod q: Montgomery form of 1
-    return w_sprp2(q, qinv, one) && w_slucas(q, qinv, one);
+    const uint32_t qi = w5_qinv(q.lo);
+    const u128w one = w_r_mod(q);   // 2^140 mod q: Montgomery form of 1
+    return w_sprp2(q, qi, one) && w_slucas(q, qi, one);
 }

@@ -113,13 +113,13 @@ __global__ __launch_bounds__(kWideThreads) void wide_probe_kernel(GbWideArgs a, 
     uint32_t k = 1;
     bool active = i < ch.cnt;
     // A lane is `ready` when its candidate primes[k] has passed the base-2
-    // test (qinv and one kept for the Lucas test).  A wave runs base-2 rounds,
+    // test (qi and one kept for the Lucas test).  A wave runs base-2 rounds,
     // in which every lane without a ready candidate scans to its next survivor
     // and tests it, until lucas_at of its active lanes are ready, then one
     // Lucas round for the ready lanes: the base-2 failures (most composite
     // survivors) then cost a base-2 test, not a whole Baillie-PSW round.
     bool ready = false;
-    uint64_t qinv = 0;
+    uint32_t qi = 0;
     u128w one = {0, 0};
     for (;;) {
         const unsigned long long act = __ballot(active);
@@ -151,9 +151,9 @@ __global__ __launch_bounds__(kWideThreads) void wide_probe_kernel(GbWideArgs a, 
                     settled = true;
                 } else {
                     const u128w q = w_sub64(n, p);
-                    qinv = w_qinv(q.lo);
+                    qi = w5_qinv(q.lo);
                     one = w_r_mod(q);
-                    if (w_sprp2(q, qinv, one))
+                    if (w_sprp2(q, qi, one))
                         ready = true;
                     else
                         ++k;
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kWideThreads) void wide_probe_kernel(GbWideArgs a, 
             const uint32_t p = a.primes[k];
             const u128w n = w_add64(ch.n0, 2ull * i);
             ready = false;
-            if (w_slucas(w_sub64(n, p), qinv, one)) {
+            if (w_slucas(w_sub64(n, p), qi, one)) {
                 sum += p;
                 ++nres;
                 max_merge_w(bp, bn, p, n);

@@ -1,0 +1,53 @@
+"""Host check of the Montgomery arithmetic over 28-bit limbs (R = 2^140) that
+the Baillie-PSW test past 2^64 runs on (gb_wide_w5.h, compiled here with g++
+as plain C++ by tests/wide_limb_arith.cpp): for seeded moduli of 64 to 128
+bits and operands at the limits of the documented bounds (limbs up to
+2^30 - 1, values up to 8q - 1), the product is congruent to a b 2^-140 mod q,
+its low limbs are normalized and its value is below a b / 2^140 + q; the
+reduction and subtraction helpers give the exact residues.  Exact integers
+decide."""
+import os
+import shutil
+import subprocess
+import tempfile
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+R = 1 << 140
+
+
+def val(limbs):
+    return sum(x << (28 * j) for j, x in enumerate(limbs))
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_limb_montgomery_product_and_helpers():
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "w5")
+        subprocess.run(["g++", "-O2", "-std=c++17", "-o", exe,
+                        os.path.join(HERE, "wide_limb_arith.cpp")], check=True)
+        out = subprocess.run([exe, "40000", "7"], capture_output=True, text=True, timeout=600,
+                             check=True).stdout.splitlines()
+    assert len(out) == 80000
+    lazy = 0
+    for mline, hline in zip(out[0::2], out[1::2]):
+        f = mline.split()
+        assert f[0] == "mont"
+        qi = int(f[1], 16)
+        ql, al, bl, rl = ([int(x, 16) for x in f[2 + 5 * k:7 + 5 * k]] for k in range(4))
+        q, a, b, r = val(ql), val(al), val(bl), val(rl)
+        assert q % 2 == 1 and (1 << 63) < q < (1 << 128)
+        assert (qi * q) % (1 << 28) == (1 << 28) - 1          # qi = -q^-1 mod 2^28
+        assert max(al + bl) < (1 << 30) and a < 8 * q and b < 8 * q
+        lazy += max(al + bl) >= (1 << 28)
+        assert (r * R - a * b) % q == 0
+        assert max(rl[:4]) < (1 << 28)
+        assert r * R < a * b + q * R                          # r < a b / R + q
+        h = hline.split()
+        assert h[0] == "help"
+        yl, zl, sl = ([int(x, 16) for x in h[1 + 5 * k:6 + 5 * k]] for k in range(3))
+        assert val(yl) == r % q and max(yl[:4]) < (1 << 28)   # canonical
+        assert val(zl) == 2 * q - r and max(zl[:4]) < (1 << 28)
+        assert val(sl) == (r + 3 * (2 * q - r)) % q
+    assert lazy > 10000   # the lazy operand forms were exercised
