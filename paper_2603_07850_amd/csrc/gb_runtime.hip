@@ -1490,7 +1490,7 @@ gb_status verify_wide_part(Ctx &c, u128h A, u128h B, uint64_t P_max, hipStream_t
             ch.bits = (uint32_t *)c.d_wbits.p;
             // lanes to gather before a Lucas round: the more of the survivors
             // are composite (larger n), the sooner (a model of the rounds)
-            ch.lucas_at = (n0 >> 112) ? 48 : (n0 >> 80) ? 52 : 60;
+            ch.lucas_at = (n0 >> 80) ? 56 : 60;
             const uint64_t words = (ch.nbits + 31) / 32;
             const uint32_t sieve_grid = (uint32_t)std::min<uint64_t>(
                 (words + kWideSieveWords - 1) / kWideSieveWords, (uint64_t)c.num_cu * 8);

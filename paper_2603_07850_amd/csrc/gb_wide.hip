@@ -18,9 +18,10 @@
 //     candidate, reads the candidate's bit from the bitmap, and runs
 //     Baillie-PSW on the first survivor (the base-2 test and the Lucas test in
 //     rounds of their own, so that lanes whose survivor fails the base-2 test
-//     do not wait through a Lucas test); a lane whose even is settled claims
-//     the next unclaimed even of the chunk (one atomic per wave and round), so
-//     every lane stays busy until the chunk runs out.
+//     do not wait through a Lucas test; two evens per lane, so that a lane
+//     whose one even waits for the Lucas round works on the other); a settled
+//     even's slot claims the next unclaimed even of the chunk (one atomic per
+//     wave and round), so every lane stays busy until the chunk runs out.
 // Survivors of the sieve to S are prime with probability about 0.9 near 2^64,
 // so an even costs about one Baillie-PSW test.  Evens that no candidate
 // p <= P_max resolves are spilled to the wide Phase-2 kernel, which continues
@@ -105,40 +106,52 @@ __global__ __launch_bounds__(kWideThreads) void wide_probe_kernel(GbWideArgs a, 
     const uint32_t *bits = ch.bits;
     uint64_t sum = 0, nres = 0, bp = 0, nsp = 0;
     u128w bn = {0, 0};
+    // A lane holds two evens (slots 0 and 1), each with its next candidate
+    // k.  A slot is `ready` when its candidate primes[k] has passed the base-2
+    // test (qi and one kept for the Lucas test).  A wave runs base-2 rounds,
+    // in which every lane with a slot lacking a ready candidate scans that
+    // slot to its next survivor and tests it, until lucas_at of its active
+    // lanes hold a ready slot, then one Lucas round in which every such lane
+    // tests one ready slot: the base-2 failures (most composite survivors)
+    // cost a base-2 test, not a whole Baillie-PSW round, and a lane whose one
+    // even is ready still has the other to work on in the base-2 rounds.
     uint64_t claim = 0;
     if (lane == 0)
-        claim = atomicAdd(&a.ctr[0], 64ull);
+        claim = atomicAdd(&a.ctr[0], 128ull);
     claim = __shfl(claim, 0, 64);
-    uint64_t i = claim + lane;
-    uint32_t k = 1;
-    bool active = i < ch.cnt;
-    // A lane is `ready` when its candidate primes[k] has passed the base-2
-    // test (qi and one kept for the Lucas test).  A wave runs base-2 rounds,
-    // in which every lane without a ready candidate scans to its next survivor
-    // and tests it, until lucas_at of its active lanes are ready, then one
-    // Lucas round for the ready lanes: the base-2 failures (most composite
-    // survivors) then cost a base-2 test, not a whole Baillie-PSW round.
-    bool ready = false;
-    uint32_t qi = 0;
-    u128w one = {0, 0};
+    bool act0 = claim + lane < ch.cnt, act1 = claim + 64 + lane < ch.cnt;
+    uint32_t i0 = (uint32_t)(claim + lane), i1 = (uint32_t)(claim + 64 + lane);   // below 2^31
+    uint32_t k0 = 1, k1 = 1, qi0 = 0, qi1 = 0;
+    bool rdy0 = false, rdy1 = false;
+    u128w one0 = {0, 0}, one1 = {0, 0};
     for (;;) {
-        const unsigned long long act = __ballot(active);
+        const bool need0 = act0 && !rdy0, need1 = act1 && !rdy1;
+        const bool has_rdy = (act0 && rdy0) || (act1 && rdy1);
+        const unsigned long long act = __ballot(act0 || act1);
         if (act == 0)
             break;
         const uint32_t nact = (uint32_t)__popcll(act);
-        const uint32_t nrdy = (uint32_t)__popcll(__ballot(active && ready));
-        bool settled = false;
-        if (nrdy < (nact < ch.lucas_at ? nact : ch.lucas_at)) {
-            if (active && !ready) {
+        const uint32_t nrdy = (uint32_t)__popcll(__ballot(has_rdy));
+        const bool base2 = nrdy < (nact < ch.lucas_at ? nact : ch.lucas_at);
+        // the slot this lane works on in this round
+        const bool s1 = base2 ? !need0 : !(act0 && rdy0);
+        const bool work = base2 ? (need0 || need1) : has_rdy;
+        const uint32_t i = s1 ? i1 : i0;
+        uint32_t k = s1 ? k1 : k0;
+        uint32_t qi = s1 ? qi1 : qi0;
+        u128w one = s1 ? one1 : one0;
+        bool ready = false, settled = false;
+        if (work) {
+            const u128w n = w_add64(ch.n0, 2ull * i);
+            if (base2) {
                 // next surviving candidate: bit(n - p) = i + H - (p - 1)/2 clear
                 uint32_t p = 0;
                 for (; k <= a.ncand; ++k) {
                     p = a.primes[k];
-                    const uint32_t b = (uint32_t)i + H - (p >> 1);
+                    const uint32_t b = i + H - (p >> 1);
                     if (((bits[b >> 5] >> (b & 31)) & 1u) == 0)
                         break;
                 }
-                const u128w n = w_add64(ch.n0, 2ull * i);
                 if (k > a.ncand) {
                     // no candidate p <= P_max: to Phase 2
                     const unsigned long long e = atomicAdd(&a.ctr[1], 1ull);
@@ -158,31 +171,48 @@ __global__ __launch_bounds__(kWideThreads) void wide_probe_kernel(GbWideArgs a, 
                     else
                         ++k;
                 }
-            }
-        } else if (active && ready) {
-            const uint32_t p = a.primes[k];
-            const u128w n = w_add64(ch.n0, 2ull * i);
-            ready = false;
-            if (w_slucas(w_sub64(n, p), qi, one)) {
-                sum += p;
-                ++nres;
-                max_merge_w(bp, bn, p, n);
-                settled = true;
             } else {
-                ++k;
+                const uint32_t p = a.primes[k];
+                if (w_slucas(w_sub64(n, p), qi, one)) {
+                    sum += p;
+                    ++nres;
+                    max_merge_w(bp, bn, p, n);
+                    settled = true;
+                } else {
+                    ++k;
+                }
+            }
+            if (s1) {
+                k1 = k;
+                qi1 = qi;
+                one1 = one;
+                rdy1 = ready;
+            } else {
+                k0 = k;
+                qi0 = qi;
+                one0 = one;
+                rdy0 = ready;
             }
         }
-        // settled lanes claim the next evens of the chunk, in lane order
-        const unsigned long long need = __ballot(active && settled);
+        // settled slots take the next evens of the chunk, in lane order
+        const unsigned long long need = __ballot(work && settled);
         if (need) {
             uint64_t base = 0;
             if (lane == 0)
                 base = atomicAdd(&a.ctr[0], (unsigned long long)__popcll(need));
             base = __shfl(base, 0, 64);
-            if (active && settled) {
-                i = base + (uint64_t)__popcll(need & ((1ull << lane) - 1));
-                k = 1;
-                active = i < ch.cnt;
+            if (work && settled) {
+                const uint64_t ni = base + (uint64_t)__popcll(need & ((1ull << lane) - 1));
+                const bool more = ni < ch.cnt;
+                if (s1) {
+                    i1 = (uint32_t)ni;
+                    k1 = 1;
+                    act1 = more;
+                } else {
+                    i0 = (uint32_t)ni;
+                    k0 = 1;
+                    act0 = more;
+                }
             }
         }
     }
