@@ -13,17 +13,18 @@
 //     each pass is written out as whole words;
 //   * the larger sieving primes, one thread each, locate their first multiple
 //     once per chunk (a 128-by-32 remainder) and OR their strikes into the
-//     bitmap with device atomics (a few per thousand bits each);
-//   * a persistent probe over all CUs: a lane holds one even and its next
-//     candidate, reads the candidate's bit from the bitmap, and runs
+//     bitmap with device atomics (about 0.56 per bit of the chunk in all);
+//   * a persistent probe over all CUs: a lane holds two evens, each with its
+//     next candidate, reads a candidate's bit from the bitmap, and runs
 //     Baillie-PSW on the first survivor (the base-2 test and the Lucas test in
 //     rounds of their own, so that lanes whose survivor fails the base-2 test
 //     do not wait through a Lucas test; two evens per lane, so that a lane
 //     whose one even waits for the Lucas round works on the other); a settled
 //     even's slot claims the next unclaimed even of the chunk (one atomic per
 //     wave and round), so every lane stays busy until the chunk runs out.
-// Survivors of the sieve to S are prime with probability about 0.9 near 2^64,
-// so an even costs about one Baillie-PSW test.  Evens that no candidate
+// A survivor of the sieve to S is prime with probability about 1.78 ln S / ln q
+// (0.8 near 2^64, 0.4 near 2^128), so an even costs one Baillie-PSW test and
+// a few base-2 tests of composite survivors.  Evens that no candidate
 // p <= P_max resolves are spilled to the wide Phase-2 kernel, which continues
 // with the table primes above P_max.
 #include "gb_wide.h"
