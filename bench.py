@@ -23,8 +23,9 @@ Extra legs (also in the JSON line):
                 batching server and through one gb_verify_range at a time, at
                 0.7x the batched capacity and saturated, every served result
                 compared with the request verified alone;
-  past_2_64     windows of 2^22 evens just above 2^64, at 2^96 and below 2^128
-                through gb_verify_range_u128 (Baillie-PSW past 2^64);
+  past_2_64     windows of 2^22 evens just above 2^64, at 2^96 and below 2^128,
+                and 2^26 evens from 2^64, through gb_verify_range_u128
+                (Baillie-PSW past 2^64);
   cpu_baseline  the CPU oracle on this host's cores over seeded 10^7-wide
                 windows of the headline range, plus single-thread rates.
 
@@ -370,22 +371,28 @@ def run_c1(gb, steps, prices=None):
 
 
 def run_past_2_64(gb, steps=3):
-    """Windows of 2^22 evens past the 64-bit ceiling (base primes <= 2^32 - 1
+    """Windows of 2^22 evens past the 64-bit ceiling (from 2^64, from 2^96 and
+    ending at 2^128 - 4) and one of 2^26 evens from 2^64 (base primes <= 2^32 - 1
     resident, P_max = 2^16): evens/s of gb_verify_range_u128 (median of
-    `steps`).  The wide oracle's single-thread rate is in cpu_baseline."""
+    `steps` calls after one untimed) and the chunk kernels' time.  The wide
+    oracle's single-thread rate is in cpu_baseline."""
     import statistics
-    n = 1 << 22
-    out = {"evens_per_window": n}
-    for label, A in (("2^64", 1 << 64), ("2^96", 1 << 96), ("2^128 - 2^23", (1 << 128) - 2 * n - 2)):
+    out = {"evens_per_window": 1 << 22}
+    n22 = 1 << 22
+    for label, A, n in (("2^64", 1 << 64, n22), ("2^96", 1 << 96, n22),
+                        ("2^128 - 2^23", (1 << 128) - 2 * n22 - 2, n22),
+                        ("2^64, 2^26 evens", 1 << 64, 1 << 26)):
         B = A + 2 * (n - 1)
         r = gb.verify_range_u128(A, B, 65536)
-        each = []
+        each, kern = [], []
         for _ in range(steps):
             t0 = time.perf_counter()
             r2 = gb.verify_range_u128(A, B, 65536)
             each.append(time.perf_counter() - t0)
+            kern.append(gb.last_stats()["probe_ms"])
         dt = statistics.median(each)
-        out[label] = {"evens_per_s": n / dt, "s_median": dt, "consistent": r2 == r,
+        out[label] = {"evens_per_s": n / dt, "s_median": dt,
+                      "kernels_ms_median": statistics.median(kern), "consistent": r2 == r,
                       "all_verified": r["verified"] == n and r["n_failed"] == 0}
     return out
 
