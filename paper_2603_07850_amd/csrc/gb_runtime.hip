@@ -1494,8 +1494,9 @@ gb_status verify_wide_part(Ctx &c, u128h A, u128h B, uint64_t P_max, hipStream_t
             const uint64_t words = (ch.nbits + 31) / 32;
             const uint32_t sieve_grid = (uint32_t)std::min<uint64_t>(
                 (words + kWideSieveWords - 1) / kWideSieveWords, (uint64_t)c.num_cu * 8);
-            // a block per 256 evens at most, so that a short chunk claims no idle blocks
-            const uint32_t grid = (uint32_t)std::min<uint64_t>(nrec, (ch.cnt + 255) / 256);
+            // a block takes 512 evens at once (two per lane): no more blocks
+            // than that fills, so that a short chunk launches no idle ones
+            const uint32_t grid = (uint32_t)std::min<uint64_t>(nrec, (ch.cnt + 511) / 512);
             grid_max = std::max(grid_max, grid);
             GB_HIP(gb_launch_wide_chunk(a, ch, sieve_grid, fill_grid, grid, s));
         }
