@@ -155,3 +155,40 @@ def test_normalization_and_refusals(gb, O):
     # and the library still gives exact results afterwards
     g = gb.verify_range_u128(2**64 + 2, 2**64 + 200, 65536)
     same(g, O.verify_range_wide(2**64 + 2, 2**64 + 200, 65536, 10**7), "after refusals")
+
+
+def test_bench_size_window_split_and_samples(gb, O):
+    """At the bench's size (2^22-even windows, here a 2^24-even range from 2^64
+    + 2 * 10^6 on the table to 2^32 - 1): the whole range in one chunk, in
+    chunks of 2^22 and as the merge of eight separate calls all agree field
+    by field, and eight seeded 512-even sub-windows equal the wide oracle."""
+    A = 2**64 + 2 * 10**6
+    n = 1 << 24
+    B = A + 2 * (n - 1)
+    print("[gpu-wide] 2^24 evens from 2^64 + 2e6, table to 2^32 - 1", flush=True)
+    gb.base_primes(2**32 - 1)
+    try:
+        whole = gb.verify_range_u128(A, B, 65536)
+        assert whole["verified"] == n and whole["n_failed"] == 0
+        gb.set_wide_chunk_log2(22)
+        try:
+            chunked = gb.verify_range_u128(A, B, 65536)
+            assert gb.last_stats()["segments"] == 4
+        finally:
+            gb.set_wide_chunk_log2(26)
+        same(chunked, whole, "chunks of 2^22")
+        merged = None
+        step = n // 8
+        for j in range(8):
+            a = A + 2 * step * j
+            r = gb.verify_range_u128(a, a + 2 * (step - 1), 65536)
+            merged = r if merged is None else O.merge(merged, r)
+        for f in ("verified", "checksum", "max_p", "max_p_n", "n_unresolved", "n_failed"):
+            assert merged[f] == whole[f], f
+        rng = random.Random(2024)
+        for _ in range(8):
+            a = A + 2 * rng.randrange(n - 512)
+            g = gb.verify_range_u128(a, a + 2 * 511, 65536)
+            same(g, O.verify_range_wide(a, a + 2 * 511, 65536, 10**7), ("sample", a))
+    finally:
+        gb.base_primes(10**7)
