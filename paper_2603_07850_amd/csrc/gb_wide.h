@@ -80,24 +80,13 @@ __device__ __forceinline__ u128w w_submod(u128w a, u128w b, u128w q)
     return r;
 }
 
-// 2^140 mod q for odd q > 1 (the Montgomery form of 1): from 2^(L-1) < q (L
-// the bit length of q), by 141 - L modular doublings.
-__device__ __forceinline__ u128w w_r_mod(u128w q)
-{
-    const int L = q.hi ? 128 - __builtin_clzll(q.hi) : 64 - __builtin_clzll(q.lo);
-    u128w x = L > 64 ? u128w{0, 1ull << (L - 65)} : u128w{1ull << (L - 1), 0};
-    for (int i = L - 1; i < 140; ++i)
-        x = w_addmod(x, x, q);
-    return x;
-}
-
-// x * c mod q for x < q and 1 <= c < 2^16, q odd with qinv_d = 1 / q in double
-// precision.  The quotient k = floor(x c / q) < 2^16 is estimated in double
+// x * c mod q for x < q and 1 <= c < 2^40, q odd with qinv_d = 1 / q in double
+// precision.  The quotient k = floor(x c / q) < 2^40 is estimated in double
 // precision: with at most seven roundings the estimate's relative error is
-// below 2^-50, so its absolute error is below 2^-34 and its floor is k - 1, k
+// below 2^-50, so its absolute error is below 2^-10 and its floor is k - 1, k
 // or k + 1.  R = x c - k' q is formed over three 64-bit words (its top word is
 // -1, 0 or 1, as R lies in [-q, 2q)) and corrected once either way.
-__device__ __forceinline__ u128w w_mul_small(u128w x, uint32_t c, u128w q, double qinv_d)
+__device__ __forceinline__ u128w w_mul_small(u128w x, uint64_t c, u128w q, double qinv_d)
 {
     const double xd = (double)x.hi * 18446744073709551616.0 + (double)x.lo;
     const double kd = __builtin_floor(xd * (double)c * qinv_d);
@@ -131,6 +120,18 @@ __device__ __forceinline__ u128w w_mul_small(u128w x, uint32_t c, u128w q, doubl
 __device__ __forceinline__ double w_recip_d(u128w q)
 {
     return 1.0 / ((double)q.hi * 18446744073709551616.0 + (double)q.lo);
+}
+
+// 2^140 mod q for odd q > 1 (the Montgomery form of 1): from 2^(L-1) < q (L
+// the bit length of q), multiplied by 2^(141 - L) in steps of at most 2^40.
+__device__ __forceinline__ u128w w_r_mod(u128w q)
+{
+    const int L = q.hi ? 128 - __builtin_clzll(q.hi) : 64 - __builtin_clzll(q.lo);
+    u128w x = L > 64 ? u128w{0, 1ull << (L - 65)} : u128w{1ull << (L - 1), 0};
+    const double qinv_d = w_recip_d(q);
+    for (int s = 141 - L; s > 0; s -= 40)
+        x = w_mul_small(x, 1ull << (s < 40 ? s : 40), q, qinv_d);
+    return x;
 }
 
 // Jacobi symbol (a / m) for odd 0 < m and 0 <= a < m, 32-bit.
