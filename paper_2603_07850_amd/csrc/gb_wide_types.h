@@ -6,10 +6,7 @@
 
 #include <cstdint>
 
-// An unsigned 128-bit integer as two 64-bit words.
-struct u128w {
-    uint64_t lo, hi;
-};
+#include "gb_wide_u128.h"
 
 // Partial aggregates of the evens one wide probe workgroup settled (summed
 // over the chunks of a call).

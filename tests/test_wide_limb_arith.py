@@ -51,3 +51,26 @@ def test_limb_montgomery_product_and_helpers():
         assert val(zl) == 2 * q - r and max(zl[:4]) < (1 << 28)
         assert val(sl) == (r + 3 * (2 * q - r)) % q
     assert lazy > 10000   # the lazy operand forms were exercised
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_u128_small_product_and_montgomery_one():
+    """gb_wide_u128.h on the host: x * c mod q for residues x (random, next to
+    q, next to multiples of q over c) and constants c of 1 to 40 bits, and
+    2^140 mod q, for seeded moduli of 64 to 128 bits; exact integers decide."""
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "u128")
+        subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-o", exe,
+                        os.path.join(HERE, "wide_u128_arith.cpp")], check=True)
+        out = subprocess.run([exe, "200000", "11"], capture_output=True, text=True, timeout=600,
+                             check=True).stdout.splitlines()
+    assert len(out) == 200000
+    near = 0
+    for line in out:
+        qh, ql, xh, xl, k, rh, rl, oh, ol = (int(v, 16) for v in line.split())
+        q, x, r, one = (qh << 64) | ql, (xh << 64) | xl, (rh << 64) | rl, (oh << 64) | ol
+        assert 0 <= x < q and 1 <= k < (1 << 40)
+        assert r == (x * k) % q, (q, x, k)
+        assert one == (1 << 140) % q, q
+        near += min((x * k) % q, q - (x * k) % q) < (q >> 40)
+    assert near > 1000   # products next to multiples of q were exercised
