@@ -1436,8 +1436,10 @@ gb_status verify_wide_part(Ctx &c, u128h A, u128h B, uint64_t P_max, hipStream_t
     const uint64_t nsieve = c.T >= (1ull << kWideSieveLog2) ? c.pi2[kWideSieveLog2] : c.nprimes;
     const uint64_t chunk = 1ull << c.wide_chunk_log2;
     const uint64_t nchunks = (nE + chunk - 1) / chunk;
-    const uint32_t occ = (uint32_t)gb_wide_occupancy();
-    const uint32_t nrec = (uint32_t)c.num_cu * occ;
+    uint32_t occ[6] = {0, 0, 0, 0, 0, 0};   // probe blocks per CU by limb count
+    for (int l = 3; l <= 5; ++l)
+        occ[l] = (uint32_t)gb_wide_occupancy(l);
+    const uint32_t nrec = (uint32_t)c.num_cu * std::max(occ[3], std::max(occ[4], occ[5]));
     const uint64_t max_words = (std::min<uint64_t>(nE, chunk) + H + 31) / 32;
     GB_TRY(c.d_wrec.reserve((uint64_t)nrec * sizeof(GbWideRecord)));
     GB_TRY(c.d_wspill.reserve(kWideSpillCap * sizeof(GbWideSpill)));
@@ -1494,11 +1496,18 @@ gb_status verify_wide_part(Ctx &c, u128h A, u128h B, uint64_t P_max, hipStream_t
             const uint64_t words = (ch.nbits + 31) / 32;
             const uint32_t sieve_grid = (uint32_t)std::min<uint64_t>(
                 (words + kWideSieveWords - 1) / kWideSieveWords, (uint64_t)c.num_cu * 8);
+            // the fewest 28-bit limbs that keep every q of the chunk (q < the
+            // chunk's last n) 12 bits below R = 2^(28 limbs)
+            const u128h nlast = n0 + 2 * (u128h)(ch.cnt - 1);
+            const int nbits_last = (nlast >> 64) ? 128 - __builtin_clzll((uint64_t)(nlast >> 64))
+                                                 : 64 - __builtin_clzll((uint64_t)nlast);
+            const int limbs = nbits_last <= 72 ? 3 : (nbits_last <= 100 ? 4 : 5);
             // a block takes 512 evens at once (two per lane): no more blocks
             // than that fills, so that a short chunk launches no idle ones
-            const uint32_t grid = (uint32_t)std::min<uint64_t>(nrec, (ch.cnt + 511) / 512);
+            const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)c.num_cu * occ[limbs],
+                                                               (ch.cnt + 511) / 512);
             grid_max = std::max(grid_max, grid);
-            GB_HIP(gb_launch_wide_chunk(a, ch, sieve_grid, fill_grid, grid, s));
+            GB_HIP(gb_launch_wide_chunk(a, ch, sieve_grid, fill_grid, limbs, grid, s));
         }
         GB_HIP(hipEventRecord(c.ev[2], s));
         GB_HIP(gb_launch_wide_phase2(a, (uint32_t)c.num_cu * 4, s));

@@ -4,14 +4,14 @@
 // symbols, and the Baillie-PSW probable-prime test (strong test to base 2,
 // then the strong Lucas test with Selfridge's parameters D = 5, -7, 9, ...;
 // P = 1, Q = (1 - D)/4, evaluated on the V sequence alone) over the Montgomery
-// arithmetic of gb_wide_w5.h (R = 2^140).
+// arithmetic of gb_wide_limbs.h (R = 2^(28 N)).
 #pragma once
 
 #include "gb_arith.h"
 #include "gb_internal.h"
 #include "gb_wide_types.h"
 #include "gb_wide_u128.h"
-#include "gb_wide_w5.h"
+#include "gb_wide_limbs.h"
 
 // a mod p for an odd prime 3 <= p < 2^32: (hi mod p) * (2^64 mod p) + lo mod p.
 __device__ __forceinline__ uint32_t w_mod_u32(u128w a, uint32_t p)
@@ -86,13 +86,14 @@ __device__ inline bool w_is_square(u128w q)
 
 // The two halves of the Baillie-PSW test of an odd q > 2^64 that has no prime
 // factor up to 97 (the sieve has removed every factor up to its bound), with
-// qi = w5_qinv(q.lo) and one = w_r_mod(q).  First the strong probable-prime
-// test to base 2:
+// N limbs for q below 2^(28 N - 12), qi = wl_qinv(q.lo) and one = 2^(28 N) mod q
+// = w_r_mod(q, 28 N).  First the strong probable-prime test to base 2:
+template <int N>
 __device__ inline bool w_sprp2(u128w q, uint32_t qi, u128w one_u)
 {
-    const w5 q5 = w5_from(q.lo, q.hi);
-    const w5 one = w5_from(one_u.lo, one_u.hi);
-    const w5 minus_one = w5_sub(q5, one);
+    const wl<N> q5 = wl_from<N>(q.lo, q.hi);
+    const wl<N> one = wl_from<N>(one_u.lo, one_u.hi);
+    const wl<N> minus_one = wl_sub(q5, one);
     // q - 1 = d * 2^s
     u128w d = w_sub64(q, 1);
     int s = 0;
@@ -102,23 +103,24 @@ __device__ inline bool w_sprp2(u128w q, uint32_t qi, u128w one_u)
         ++s;
     }
     const int top = d.hi ? 127 - __builtin_clzll(d.hi) : 63 - __builtin_clzll(d.lo);
-    w5 x = one;
+    wl<N> x = one;
     for (int i = top; i >= 0; --i) {
-        x = w5_mont(x, x, q5, qi);                 // below 1.01 q
+        x = wl_mont(x, x, q5, qi);                 // below 1.02 q
         const uint64_t w = i >= 64 ? d.hi : d.lo;
         if ((w >> (i & 63)) & 1)
-            x = w5_add(x, x);                      // times the base 2: below 2.02 q
+            x = wl_add(x, x);                      // times the base 2: below 2.04 q
     }
-    x = w5_canon<2>(x, q5);
-    bool pass = w5_eq(x, one) || w5_eq(x, minus_one);
+    x = wl_canon<N, 2>(x, q5);
+    bool pass = wl_eq(x, one) || wl_eq(x, minus_one);
     for (int r = 1; r < s && !pass; ++r) {
-        x = w5_canon<1>(w5_mont(x, x, q5, qi), q5);
-        pass = w5_eq(x, minus_one);
+        x = wl_canon<N, 1>(wl_mont(x, x, q5, qi), q5);
+        pass = wl_eq(x, minus_one);
     }
     return pass;
 }
 
 // then the strong Lucas test with Selfridge's parameters.
+template <int N>
 __device__ inline bool w_slucas(u128w q, uint32_t qi, u128w one_u)
 {
     // Selfridge: the first D of 5, -7, 9, -11, ... with (D / q) = -1
@@ -161,45 +163,53 @@ __device__ inline bool w_slucas(u128w q, uint32_t qi, u128w one_u)
     // ((D / q) = -1), so U_d = 0 (mod q) exactly when 2 V_d+1 = P V_d.  Every
     // step is the same four Montgomery products whatever the bit (no
     // divergence); the subtractions are additions of 2q - Q^k and
-    // 2 (2q - Q^(k+bit)), so V_k and V_k+1 stay below 5.01 q unreduced.
-    const w5 q5 = w5_from(q.lo, q.hi);
-    const w5 twoq = w5_norm(w5_add(q5, q5));
-    const w5 Qm = w5_from(Qm_u.lo, Qm_u.hi);
+    // 2 (2q - Q^(k+bit)), so V_k and V_k+1 stay below 5.02 q unreduced.
+    const wl<N> q5 = wl_from<N>(q.lo, q.hi);
+    const wl<N> twoq = wl_norm(wl_add(q5, q5));
+    const wl<N> Qm = wl_from<N>(Qm_u.lo, Qm_u.hi);
     const int top = d.hi ? 127 - __builtin_clzll(d.hi) : 63 - __builtin_clzll(d.lo);
-    w5 V = w5_from(one_u.lo, one_u.hi);   // V_1 = P = 1
-    w5 V1 = w5_from(V2_u.lo, V2_u.hi);    // V_2
-    w5 Qk = Qm;                           // Q^1
+    wl<N> V = wl_from<N>(one_u.lo, one_u.hi);   // V_1 = P = 1
+    wl<N> V1 = wl_from<N>(V2_u.lo, V2_u.hi);    // V_2
+    wl<N> Qk = Qm;                              // Q^1
     for (int i = top - 1; i >= 0; --i) {
         const uint64_t w = i >= 64 ? d.hi : d.lo;
         const bool bit = ((w >> (i & 63)) & 1) != 0;
-        const w5 QkQ = w5_mont(Qk, Qm, q5, qi);
-        const w5 Qb = bit ? QkQ : Qk;     // Q^(k + bit), below 1.01 q
-        const w5 x = bit ? V1 : V;
-        const w5 prod = w5_add(w5_mont(V, V1, q5, qi), w5_sub(twoq, Qk));
-        const w5 nb = w5_sub(twoq, Qb);
-        const w5 sq = w5_add(w5_mont(x, x, q5, qi), w5_add(nb, nb));
+        const wl<N> QkQ = wl_mont(Qk, Qm, q5, qi);
+        const wl<N> Qb = bit ? QkQ : Qk;        // Q^(k + bit), below 1.02 q
+        const wl<N> x = bit ? V1 : V;
+        const wl<N> prod = wl_add(wl_mont(V, V1, q5, qi), wl_sub(twoq, Qk));
+        const wl<N> nb = wl_sub(twoq, Qb);
+        const wl<N> sq = wl_add(wl_mont(x, x, q5, qi), wl_add(nb, nb));
         V = bit ? prod : sq;
         V1 = bit ? sq : prod;
-        Qk = w5_mont(Qk, Qb, q5, qi);     // Q^(2k + bit)
+        Qk = wl_mont(Qk, Qb, q5, qi);           // Q^(2k + bit)
     }
-    V = w5_canon<5>(V, q5);
-    V1 = w5_canon<5>(V1, q5);
-    if (w5_eq(w5_canon<1>(w5_add(V1, V1), q5), V) || w5_zero(V))
+    V = wl_canon<N, 5>(V, q5);
+    V1 = wl_canon<N, 5>(V1, q5);
+    if (wl_eq(wl_canon<N, 1>(wl_add(V1, V1), q5), V) || wl_zero(V))
         return true;   // U_d = 0 or V_d = 0
     for (int r = 1; r < s; ++r) {
-        const w5 nq = w5_sub(twoq, Qk);
-        V = w5_canon<5>(w5_add(w5_mont(V, V, q5, qi), w5_add(nq, nq)), q5);
-        Qk = w5_mont(Qk, Qk, q5, qi);
-        if (w5_zero(V))
+        const wl<N> nq = wl_sub(twoq, Qk);
+        V = wl_canon<N, 5>(wl_add(wl_mont(V, V, q5, qi), wl_add(nq, nq)), q5);
+        Qk = wl_mont(Qk, Qk, q5, qi);
+        if (wl_zero(V))
             return true;
     }
     return false;
 }
 
-// Baillie-PSW: both halves.
+// Baillie-PSW: both halves, over the fewest limbs for q.
+template <int N>
+__device__ inline bool w_bpsw_n(u128w q)
+{
+    const uint32_t qi = wl_qinv(q.lo);
+    const u128w one = w_r_mod(q, 28 * N);   // Montgomery form of 1
+    return w_sprp2<N>(q, qi, one) && w_slucas<N>(q, qi, one);
+}
+
 __device__ inline bool w_bpsw(u128w q)
 {
-    const uint32_t qi = w5_qinv(q.lo);
-    const u128w one = w_r_mod(q);   // 2^140 mod q: Montgomery form of 1
-    return w_sprp2(q, qi, one) && w_slucas(q, qi, one);
+    const int L = q.hi ? 128 - __builtin_clzll(q.hi) : 64 - __builtin_clzll(q.lo);
+    const int n = wl_limbs_for(L);
+    return n == 3 ? w_bpsw_n<3>(q) : (n == 4 ? w_bpsw_n<4>(q) : w_bpsw_n<5>(q));
 }

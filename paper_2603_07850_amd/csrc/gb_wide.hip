@@ -96,7 +96,10 @@ __global__ __launch_bounds__(256) void wide_large_fill_kernel(GbWideArgs a, GbWi
     }
 }
 
-// The probe of one chunk (persistent; the records accumulate over the chunks).
+// The probe of one chunk (persistent; the records accumulate over the chunks),
+// its Baillie-PSW arithmetic over N 28-bit limbs (every q of the chunk below
+// 2^(28 N - 12)).
+template <int N>
 __global__ __launch_bounds__(kWideThreads) void wide_probe_kernel(GbWideArgs a, GbWideChunk ch)
 {
     constexpr uint32_t NWAVE = kWideThreads / 64;
@@ -165,16 +168,16 @@ __global__ __launch_bounds__(kWideThreads) void wide_probe_kernel(GbWideArgs a, 
                     settled = true;
                 } else {
                     const u128w q = w_sub64(n, p);
-                    qi = w5_qinv(q.lo);
-                    one = w_r_mod(q);
-                    if (w_sprp2(q, qi, one))
+                    qi = wl_qinv(q.lo);
+                    one = w_r_mod(q, 28 * N);
+                    if (w_sprp2<N>(q, qi, one))
                         ready = true;
                     else
                         ++k;
                 }
             } else {
                 const uint32_t p = a.primes[k];
-                if (w_slucas(w_sub64(n, p), qi, one)) {
+                if (w_slucas<N>(w_sub64(n, p), qi, one)) {
                     sum += p;
                     ++nres;
                     max_merge_w(bp, bn, p, n);
@@ -412,7 +415,7 @@ __global__ __launch_bounds__(256) void bpsw_kernel(const u128w *q, uint64_t coun
 }  // namespace
 
 hipError_t gb_launch_wide_chunk(const GbWideArgs &a, const GbWideChunk &ch, uint32_t sieve_grid,
-                                uint32_t fill_grid, uint32_t grid, hipStream_t s)
+                                uint32_t fill_grid, int limbs, uint32_t grid, hipStream_t s)
 {
     hipLaunchKernelGGL(wide_small_sieve_kernel, dim3(sieve_grid), dim3(256), 0, s, a, ch);
     hipError_t e = hipGetLastError();
@@ -424,15 +427,26 @@ hipError_t gb_launch_wide_chunk(const GbWideArgs &a, const GbWideChunk &ch, uint
         if (e != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL(wide_probe_kernel, dim3(grid), dim3(kWideThreads), 0, s, a, ch);
+    if (limbs == 3)
+        hipLaunchKernelGGL(wide_probe_kernel<3>, dim3(grid), dim3(kWideThreads), 0, s, a, ch);
+    else if (limbs == 4)
+        hipLaunchKernelGGL(wide_probe_kernel<4>, dim3(grid), dim3(kWideThreads), 0, s, a, ch);
+    else
+        hipLaunchKernelGGL(wide_probe_kernel<5>, dim3(grid), dim3(kWideThreads), 0, s, a, ch);
     return hipGetLastError();
 }
 
-int gb_wide_occupancy()
+int gb_wide_occupancy(int limbs)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wide_probe_kernel, kWideThreads, 0) !=
-        hipSuccess) {
+    const hipError_t e =
+        limbs == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wide_probe_kernel<3>,
+                                                                   kWideThreads, 0)
+        : limbs == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wide_probe_kernel<4>,
+                                                                     kWideThreads, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wide_probe_kernel<5>,
+                                                                     kWideThreads, 0);
+    if (e != hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }

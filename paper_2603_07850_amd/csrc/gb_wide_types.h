@@ -66,10 +66,13 @@ constexpr uint32_t kWideChunkLog2Min = 12, kWideChunkLog2Max = 30;
 
 // The three kernels of one chunk: the primes below 2^16 struck in LDS and
 // written as whole words, then the larger sieving primes OR-ed in by atomics,
-// then the persistent probe (grid blocks, at most a.nrec).
+// then the persistent probe (grid blocks, at most a.nrec) with its arithmetic
+// over `limbs` 28-bit limbs (3, 4 or 5: every q of the chunk below
+// 2^(28 limbs - 12)).
 hipError_t gb_launch_wide_chunk(const GbWideArgs &a, const GbWideChunk &ch, uint32_t sieve_grid,
-                                uint32_t fill_grid, uint32_t grid, hipStream_t s);
-int gb_wide_occupancy();
+                                uint32_t fill_grid, int limbs, uint32_t grid, hipStream_t s);
+// Probe blocks per CU for the given limb count.
+int gb_wide_occupancy(int limbs);
 hipError_t gb_launch_wide_phase2(const GbWideArgs &a, uint32_t grid, hipStream_t s);
 hipError_t gb_launch_wide_reduce(const GbWideArgs &a, uint64_t P_max, GbWideResult *res,
                                  u128w *unres, hipStream_t s);

@@ -1,8 +1,8 @@
 // gb_wide_u128.h -- unsigned 128-bit arithmetic of the verification past 2^64
 // as two 64-bit words: comparisons, sums and differences, residues modulo an
 // odd q, the product of a residue by a constant below 2^40 with a
-// double-precision quotient estimate, and 2^140 mod q (the Montgomery form of
-// 1 for gb_wide_w5.h).
+// double-precision quotient estimate, and 2^(28 N) mod q (the Montgomery form
+// of 1 for gb_wide_limbs.h).
 //
 // Plain integer and double code: device functions in the kernels, and host
 // functions in the tests (GB_WIDE_FN and __umul64hi defined before inclusion).
@@ -116,15 +116,15 @@ GB_WIDE_FN double w_recip_d(u128w q)
     return 1.0 / ((double)q.hi * 18446744073709551616.0 + (double)q.lo);
 }
 
-// 2^140 mod q for odd q > 1 (the Montgomery form of 1): from 2^(L-1) < q (L
-// the bit length of q), multiplied by 2^(141 - L) in steps of at most 2^40.
-GB_WIDE_FN u128w w_r_mod(u128w q)
+// 2^rbits mod q for odd q > 1 and rbits >= the bit length L of q (the
+// Montgomery form of 1 for R = 2^rbits): from 2^(L-1) < q, multiplied by
+// 2^(rbits + 1 - L) in steps of at most 2^40.
+GB_WIDE_FN u128w w_r_mod(u128w q, int rbits)
 {
     const int L = q.hi ? 128 - __builtin_clzll(q.hi) : 64 - __builtin_clzll(q.lo);
     u128w x = L > 64 ? u128w{0, 1ull << (L - 65)} : u128w{1ull << (L - 1), 0};
     const double qinv_d = w_recip_d(q);
-    for (int s = 141 - L; s > 0; s -= 40)
+    for (int s = rbits + 1 - L; s > 0; s -= 40)
         x = w_mul_small(x, 1ull << (s < 40 ? s : 40), q, qinv_d);
     return x;
 }
-

@@ -1,7 +1,7 @@
 // Host driver for the 128-bit helpers of the verification past 2^64
 // (paper_2603_07850_amd/csrc/gb_wide_u128.h, compiled here as plain C++): the
 // product of a residue by a constant below 2^40 reduced with a double-precision
-// quotient estimate, and 2^140 mod q.  Seeded cases -- moduli of 64 to 128 bits,
+// quotient estimate, and 2^(28 N) mod q.  Seeded cases -- moduli of 64 to 128 bits,
 // residues near q, products next to multiples of q, constants of 1 to 40 bits
 // and the small constants of the Lucas setup -- are printed in hex for
 // tests/test_wide_limb_arith.py to check with exact integers.
@@ -59,10 +59,13 @@ int main(int argc, char **argv)
         }
         const u128w xw = {(uint64_t)x, (uint64_t)(x >> 64)};
         const u128w r = w_mul_small(xw, k, qw, qinv);
-        const u128w one = w_r_mod(qw);
-        printf("%llx %llx %llx %llx %llx %llx %llx %llx %llx\n", (unsigned long long)qw.hi,
+        // R = 2^(28 N) for the limb count the probe gives q (N = 3, 4, 5 below
+        // 2^72, 2^100, 2^128)
+        const int rbits = bits <= 72 ? 84 : (bits <= 100 ? 112 : 140);
+        const u128w one = w_r_mod(qw, rbits);
+        printf("%llx %llx %llx %llx %llx %llx %llx %d %llx %llx\n", (unsigned long long)qw.hi,
                (unsigned long long)qw.lo, (unsigned long long)xw.hi, (unsigned long long)xw.lo,
-               (unsigned long long)k, (unsigned long long)r.hi, (unsigned long long)r.lo,
+               (unsigned long long)k, (unsigned long long)r.hi, (unsigned long long)r.lo, rbits,
                (unsigned long long)one.hi, (unsigned long long)one.lo);
     }
     return 0;
