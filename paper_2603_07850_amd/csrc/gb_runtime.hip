@@ -1432,7 +1432,8 @@ gb_status verify_wide_part(Ctx &c, u128h A, u128h B, uint64_t P_max, hipStream_t
     const uint64_t nc = small_count_le(c, pc);
     const uint32_t ncand = (uint32_t)(nc > 0 ? nc - 1 : 0);
     const uint32_t hmax = ncand ? (c.small[ncand] - 1) / 2 : 0;
-    const uint32_t H = std::max<uint32_t>(32, (hmax + 31) / 32 * 32);
+    // the probe reads 32 strikes below bit(n - p) at once: 32 bits of halo more
+    const uint32_t H = (hmax + 32 + 31) / 32 * 32;
     const uint64_t nsieve = c.T >= (1ull << kWideSieveLog2) ? c.pi2[kWideSieveLog2] : c.nprimes;
     const uint64_t chunk = 1ull << c.wide_chunk_log2;
     const uint64_t nchunks = (nE + chunk - 1) / chunk;
@@ -1440,7 +1441,7 @@ gb_status verify_wide_part(Ctx &c, u128h A, u128h B, uint64_t P_max, hipStream_t
     for (int l = 3; l <= 5; ++l)
         occ[l] = (uint32_t)gb_wide_occupancy(l);
     const uint32_t nrec = (uint32_t)c.num_cu * std::max(occ[3], std::max(occ[4], occ[5]));
-    const uint64_t max_words = (std::min<uint64_t>(nE, chunk) + H + 31) / 32;
+    const uint64_t max_words = (std::min<uint64_t>(nE, chunk) + H + 31) / 32 + 1;   // + a spare
     GB_TRY(c.d_wrec.reserve((uint64_t)nrec * sizeof(GbWideRecord)));
     GB_TRY(c.d_wspill.reserve(kWideSpillCap * sizeof(GbWideSpill)));
     GB_TRY(c.d_wunres.reserve(kWideSpillCap * sizeof(u128w)));
@@ -1457,6 +1458,7 @@ gb_status verify_wide_part(Ctx &c, u128h A, u128h B, uint64_t P_max, hipStream_t
     a.nsieve = (uint32_t)nsieve;
     a.ncand = ncand;
     a.H = H;
+    a.hmax = hmax;
     // primes[1 ..) below 2^16 and below 2^12 (every table holds the primes below 2^16)
     a.nsmall = (uint32_t)std::min<uint64_t>(nsieve, small_count_le(c, 65535));
     a.ncoop = (uint32_t)std::min<uint64_t>(a.nsmall, small_count_le(c, 4095));

@@ -105,14 +105,25 @@ __global__ __launch_bounds__(kWideThreads) void wide_probe_kernel(GbWideArgs a, 
     constexpr uint32_t NWAVE = kWideThreads / 64;
     __shared__ uint64_t red_sum[NWAVE], red_cnt[NWAVE], red_p[NWAVE], red_nl[NWAVE],
         red_nh[NWAVE], red_sp[NWAVE];
+    // bit h: 2h + 1 is a candidate (an odd prime <= P_max); one spare word
+    __shared__ uint32_t cand[kWideCandWords + 1];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t H = a.H;
+    const uint32_t H = a.H, hmax = a.hmax;
     const uint32_t *bits = ch.bits;
+    for (uint32_t t = tid; t <= kWideCandWords; t += kWideThreads)
+        cand[t] = 0;
+    __syncthreads();
+    for (uint32_t t = 1 + tid; t <= a.ncand; t += kWideThreads) {
+        const uint32_t h = a.primes[t] >> 1;
+        atomicOr(&cand[h >> 5], 1u << (h & 31));
+    }
+    __syncthreads();
     uint64_t sum = 0, nres = 0, bp = 0, nsp = 0;
     u128w bn = {0, 0};
-    // A lane holds two evens (slots 0 and 1), each with its next candidate
-    // k.  A slot is `ready` when its candidate primes[k] has passed the base-2
-    // test (qi and one kept for the Lucas test).  A wave runs base-2 rounds,
+    // A lane holds two evens (slots 0 and 1), each with a half-offset h: the
+    // candidates p = 2h + 1 below it are settled.  A slot is `ready` when its
+    // candidate 2h + 1 has passed the base-2 test (qi and one kept for the
+    // Lucas test).  A wave runs base-2 rounds,
     // in which every lane with a slot lacking a ready candidate scans that
     // slot to its next survivor and tests it, until lucas_at of its active
     // lanes hold a ready slot, then one Lucas round in which every such lane
@@ -125,7 +136,7 @@ __global__ __launch_bounds__(kWideThreads) void wide_probe_kernel(GbWideArgs a, 
     claim = __shfl(claim, 0, 64);
     bool act0 = claim + lane < ch.cnt, act1 = claim + 64 + lane < ch.cnt;
     uint32_t i0 = (uint32_t)(claim + lane), i1 = (uint32_t)(claim + 64 + lane);   // below 2^31
-    uint32_t k0 = 1, k1 = 1, qi0 = 0, qi1 = 0;
+    uint32_t k0 = 1, k1 = 1, qi0 = 0, qi1 = 0;   // half-offsets: p = 3 first
     bool rdy0 = false, rdy1 = false;
     u128w one0 = {0, 0}, one1 = {0, 0};
     for (;;) {
@@ -148,15 +159,29 @@ __global__ __launch_bounds__(kWideThreads) void wide_probe_kernel(GbWideArgs a, 
         if (work) {
             const u128w n = w_add64(ch.n0, 2ull * i);
             if (base2) {
-                // next surviving candidate: bit(n - p) = i + H - (p - 1)/2 clear
-                uint32_t p = 0;
-                for (; k <= a.ncand; ++k) {
-                    p = a.primes[k];
-                    const uint32_t b = i + H - (p >> 1);
-                    if (((bits[b >> 5] >> (b & 31)) & 1u) == 0)
+                // next surviving candidate, 32 half-offsets h at a time:
+                // bit(n - p) = i + H - h for p = 2h + 1, so the 32 bits from
+                // i + H - h - 31 up, reversed, are the strikes of h, h + 1, ...,
+                // h + 31 (H >= hmax + 32 keeps the first bit at or above 0; the
+                // bitmap has a spare word for the pair read)
+                bool hit = false;
+                while (k <= hmax) {
+                    const uint32_t b0 = i + H - k - 31;
+                    const uint32_t w = b0 >> 5;
+                    const uint64_t pair = ((uint64_t)bits[w + 1] << 32) | bits[w];
+                    const uint32_t struck = __builtin_bitreverse32((uint32_t)(pair >> (b0 & 31)));
+                    const uint32_t cw = k >> 5;
+                    const uint64_t cpair = ((uint64_t)cand[cw + 1] << 32) | cand[cw];
+                    const uint32_t surv = (uint32_t)(cpair >> (k & 31)) & ~struck;
+                    if (surv) {
+                        k += (uint32_t)__builtin_ctz(surv);
+                        hit = true;
                         break;
+                    }
+                    k += 32;
                 }
-                if (k > a.ncand) {
+                const uint32_t p = 2 * k + 1;
+                if (!hit) {
                     // no candidate p <= P_max: to Phase 2
                     const unsigned long long e = atomicAdd(&a.ctr[1], 1ull);
                     if (e < a.spill_cap) {
@@ -176,7 +201,7 @@ __global__ __launch_bounds__(kWideThreads) void wide_probe_kernel(GbWideArgs a, 
                         ++k;
                 }
             } else {
-                const uint32_t p = a.primes[k];
+                const uint32_t p = 2 * k + 1;
                 if (w_slucas<N>(w_sub64(n, p), qi, one)) {
                     sum += p;
                     ++nres;

@@ -36,7 +36,8 @@ struct GbWideArgs {
     uint64_t nprimes;
     uint32_t nsieve;      // primes[1 .. nsieve) are sieved out of every window
     uint32_t ncand;       // candidates primes[1 .. ncand]
-    uint32_t H;           // halo bits: (largest candidate - 1) / 2, rounded up to 32
+    uint32_t H;           // halo bits: hmax + 32, rounded up to a multiple of 32
+    uint32_t hmax;        // (largest candidate - 1) / 2 (0: no candidate)
     uint32_t nsmall;      // primes[1 .. nsmall) (below 2^16) are struck in LDS
     uint32_t ncoop;       // primes[1 .. ncoop) (below 2^12) are struck by a whole wave
     uint32_t nrec;        // probe records (the probe grid's upper bound)
@@ -55,11 +56,12 @@ struct GbWideChunk {
     u128w qlo;            // n0 - 1 - 2H
     uint32_t cnt;
     uint32_t nbits;
-    uint32_t *bits;       // ceil(nbits / 32) words; bit b set: q_lo + 2b has a factor <= S
+    uint32_t *bits;       // ceil(nbits / 32) words and a spare one; bit b set: q_lo + 2b has a factor <= S
     uint32_t lucas_at;    // a wave runs its Lucas round once this many lanes are ready
 };
 
 constexpr int kWideThreads = 256;
+constexpr uint32_t kWideCandWords = 1024;    // the probe's table of candidate half-offsets below 2^15
 constexpr uint32_t kWideSieveWords = 1024;   // bitmap words per LDS pass of the small primes
 constexpr uint32_t kWideChunkLog2Default = 26;
 constexpr uint32_t kWideChunkLog2Min = 12, kWideChunkLog2Max = 30;
