@@ -97,13 +97,38 @@ KERNEL_SOURCES = ("paper_2603_07850_amd/csrc/gb_sieve.hip", "paper_2603_07850_am
                   "paper_2603_07850_amd/csrc/gb_internal.h")
 
 
-def kernel_sha():
+WIDE_SOURCES = ("paper_2603_07850_amd/csrc/gb_wide.hip", "paper_2603_07850_amd/csrc/gb_wide.h",
+                "paper_2603_07850_amd/csrc/gb_wide_limbs.h",
+                "paper_2603_07850_amd/csrc/gb_wide_u128.h",
+                "paper_2603_07850_amd/csrc/gb_wide_types.h")
+
+
+def kernel_sha(sources=KERNEL_SOURCES):
     import hashlib
     sha = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             sha.update(fh.read())
     return sha.hexdigest()[:16]
+
+
+def wide_profile_figures():
+    """Counter figures of the probe past 2^64 from the committed summary (the
+    window of 2^26 evens from 2^64), None when its sources changed since."""
+    import re
+    path = os.path.join(ROOT, "profiles", "wide_probe_2_64.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    h = re.search(r"wide_kernel_source_sha256_16: ([0-9a-f]+)", text)
+    if not h or h.group(1) != kernel_sha(WIDE_SOURCES):
+        return None
+    out = {}
+    for key in ("valu_instructions_per_even_2_26", "valu_issue_frac_2_26"):
+        m = re.search(r"%s: ([0-9.]+)" % key, text)
+        if m:
+            out[key] = float(m.group(1))
+    return out if len(out) == 2 else None
 
 
 def profile_figures():
@@ -394,6 +419,20 @@ def run_past_2_64(gb, steps=3):
         out[label] = {"evens_per_s": n / dt, "s_median": dt,
                       "kernels_ms_median": statistics.median(kern), "consistent": r2 == r,
                       "all_verified": r["verified"] == n and r["n_failed"] == 0}
+    # the probe is bound by integer VALU issue: the counters of the 2^26-even
+    # window (instructions issued per even, and issued over one wave64 VALU
+    # instruction per CU per cycle), and the issue rate they imply over the
+    # timed window's kernels (the chunk's sieve and fill, ~5 %, included)
+    fig = wide_profile_figures()
+    if fig:
+        k_s = out["2^64, 2^26 evens"]["kernels_ms_median"] / 1e3
+        issued = 64 * fig["valu_instructions_per_even_2_26"] * (1 << 26) / k_s
+        out["roofline"] = {"bound": "alu", "kernel": "wide_probe_kernel<3>",
+                           "workload": "2^26 evens from 2^64",
+                           "valu_instructions_per_even": fig["valu_instructions_per_even_2_26"],
+                           "issued_TOPs": issued / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                           "unit": "TOP/s", "issue_frac": issued / VALU_PEAK_OPS,
+                           "valu_issue_frac_counters": fig["valu_issue_frac_2_26"]}
     return out
 
 
