@@ -1,7 +1,8 @@
 """GPU parity past 2^64: gb_verify_range_u128 and gb_is_prime_u128 through the
 C ABI against the wide CPU oracle (oracle/gb_oracle_wide.c), field by field,
-bit-exact: windows just above 2^64, at 2^80, 2^100, 2^127 and at the top of
-the u128 range, a range straddling 2^64 (the part below goes through the
+bit-exact: windows just above 2^64, at and across 2^72 and 2^100 (where the
+arithmetic changes its limb count), at 2^80, 2^127 and at the top of the u128
+range, a range straddling 2^64 (the part below goes through the
 64-bit path), one range cut into chunks of three sizes with ragged tails, tiny P_max with
 Phase 2 and unresolved lists, normalization and refusals."""
 import concurrent.futures as cf
@@ -71,8 +72,11 @@ def test_device_primality_u128(gb, O):
         assert g == O.bpsw(v), v
 
 
-WINDOWS = [2**64, 2**64 + 2 * 123457, 2**80 + 2 * 77, 2**100, 2**127 + 2**64 + 6,
-           2**128 - 2 * 1500]
+# 2^72 and 2^100 are where the probe's arithmetic moves from 3 to 4 and from 4
+# to 5 limbs (chosen per chunk by its last n): windows ending just below them
+# and windows across them
+WINDOWS = [2**64, 2**64 + 2 * 123457, 2**72 - 2 * 1500, 2**72 - 2 * 700, 2**80 + 2 * 77,
+           2**100 - 2 * 1500, 2**100 - 2 * 700, 2**100, 2**127 + 2**64 + 6, 2**128 - 2 * 1500]
 
 
 @pytest.mark.parametrize("A", WINDOWS, ids=lambda a: "2^%.2f" % (a.bit_length() - 1))
