@@ -196,3 +196,16 @@ def test_bench_size_window_split_and_samples(gb, O):
             same(g, O.verify_range_wide(a, a + 2 * 511, 65536, 10**7), ("sample", a))
     finally:
         gb.base_primes(10**7)
+
+
+def test_spill_cap_refusal_and_recovery(gb, O):
+    """P_max = 3 over 2^17 evens from 2^64 leaves far more than 65536 evens to
+    Phase 2: the call refuses with GB_ENOMEM and says why, and the next call is
+    exact."""
+    A = 2**64 + 2 * 10**5
+    print("[gpu-wide] P_max 3 over 2^17 evens", flush=True)
+    with pytest.raises(gb.GoldbachError) as e:
+        gb.verify_range_u128(A, A + 2 * ((1 << 17) - 1), 3)
+    assert e.value.name == "GB_ENOMEM" and "raise P_max" in str(e.value)
+    g = gb.verify_range_u128(A, A + 2 * 999, 65536)
+    same(g, O.verify_range_wide(A, A + 2 * 999, 65536, 10**7), "after the refusal")
