@@ -24,7 +24,7 @@ def val(limbs):
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 def test_limb_montgomery_product_and_helpers():
     with tempfile.TemporaryDirectory() as d:
-        exe = os.path.join(d, "w5")
+        exe = os.path.join(d, "limbs")
         subprocess.run(["g++", "-O2", "-std=c++17", "-o", exe,
                         os.path.join(HERE, "wide_limb_arith.cpp")], check=True)
         out = subprocess.run([exe, "40000", "7"], capture_output=True, text=True, timeout=600,
