@@ -18,7 +18,9 @@ Extra legs (also in the JSON line):
   c1            every even n in [4, 10^10] (base primes <= 10^5);
   batched       4096 seeded uneven intervals reaching 2^64 - 2 in one
                 persistent launch (median of 5 launches, with the 2^32 table
-                build end to end) vs one launch per interval;
+                build end to end) vs one launch per interval; its roofline is
+                the VALU instructions the counters saw in one launch over the
+                launch's device time (HIP events), per kernel beside it;
   served        the seeded Poisson request trace through the continuous-
                 batching server and through one gb_verify_range at a time, at
                 0.7x the batched capacity and saturated, every served result
@@ -131,6 +133,68 @@ def wide_profile_figures():
     return out if len(out) == 2 else None
 
 
+BATCH_SOURCES = KERNEL_SOURCES + ("paper_2603_07850_amd/csrc/gb_bucket.hip",)
+BATCH_KEYS = ("batch_evens_per_launch", "fill_valu_instructions_per_launch", "fill_ms_counters",
+              "sieve_valu_instructions_per_launch", "sieve_ms_counters",
+              "launch_valu_instructions", "launch_ms_counters",
+              "fill_first_multiples_per_launch")
+
+
+def batch_profile_figures():
+    """Counter figures of one launch of the 4096-interval batch from the
+    committed summary (launch parameters and figures), None when the kernel
+    sources changed since."""
+    import re
+    path = os.path.join(ROOT, "profiles", "batched_4096.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    h = re.search(r"batch_kernel_source_sha256_16: ([0-9a-f]+)", text)
+    pr = re.search(r"batch_profile_params: ([0-9,]+)", text)
+    if not h or not pr or h.group(1) != kernel_sha(BATCH_SOURCES):
+        return None
+    out = {"params": [int(x) for x in pr.group(1).split(",")]}
+    for key in BATCH_KEYS:
+        m = re.search(r"%s: ([0-9.e+]+)" % key, text)
+        if not m:
+            return None
+        out[key] = float(m.group(1))
+    return out
+
+
+def batch_roofline(params, evens, launch_ms):
+    """The batched launch against the VALU issue peak: the VALU instructions
+    the counters saw in one launch of this batch, issued over the launch's
+    device time (HIP events around the graph launch); per kernel, the
+    counters' own busy time.  None unless the figures are current and were
+    taken with these launch parameters."""
+    fig = batch_profile_figures()
+    if not fig or fig["batch_evens_per_launch"] != evens:
+        return None
+    p = [params["seg_log2"], params["wg_size"], params["window"],
+         params["bucket_log2"] or params["seg_log2"] + 4]   # 0: the automatic bound
+    if p != fig["params"]:
+        return None
+    issued = 64 * fig["launch_valu_instructions"] / (launch_ms / 1e3)
+    per = {}
+    for name, key in (("bucket_fill_kernel", "fill"), ("sieve_probe_kernel", "sieve")):
+        ms = fig[key + "_ms_counters"]
+        per[name] = {"valu_instructions": fig[key + "_valu_instructions_per_launch"],
+                     "ms_counters": ms,
+                     "issue_frac": 64 * fig[key + "_valu_instructions_per_launch"] /
+                                   (ms / 1e3) / VALU_PEAK_OPS}
+    # the fill's algorithmic unit: one first multiple per (interval, table prime
+    # above the bitmap bound up to isqrt(B)), from the work model
+    per["bucket_fill_kernel"]["first_multiples"] = fig["fill_first_multiples_per_launch"]
+    per["bucket_fill_kernel"]["first_multiples_per_s"] = (
+        fig["fill_first_multiples_per_launch"] / (fig["fill_ms_counters"] / 1e3))
+    return {"bound": "alu", "kernel": "bucket_fill_kernel + sieve_probe_kernel (one graph launch)",
+            "achieved": issued / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
+            "frac": issued / VALU_PEAK_OPS, "launch_ms_median": launch_ms,
+            "valu_instructions_per_launch": fig["launch_valu_instructions"],
+            "per_kernel": per, "traffic": None}
+
+
 def profile_figures():
     """Counter figures of the sieve+probe kernel from the committed summary:
     HBM bytes per launch, the VALU issue fraction and the unit prices, each
@@ -228,12 +292,15 @@ def run_batched(gb, steps, per_interval=True, tune=False):
         log("batched: tuning on every 8th interval")
         gb.autotune_batch(ivs[::8], 65536)
     gb.verify_batch(ivs[:64], 65536)
-    each = []
+    each, dev = [], []
     for _ in range(steps):
         t0 = time.perf_counter()
         res = gb.verify_batch(ivs, 65536)
         each.append(time.perf_counter() - t0)
+        dev.append(gb.last_stats()["total_ms"])
     dt = statistics.median(each)
+    dev_ms = statistics.median(dev)
+    params = gb.get_params()
     lat = gb.last_batch_latencies()
     # end to end: the 2^32 table build and one launch
     t0 = time.perf_counter()
@@ -253,7 +320,9 @@ def run_batched(gb, steps, per_interval=True, tune=False):
            "device_completion_p99_ms": q(lat, 0.99) * 1e3,
            "all_verified": all(r["n_failed"] == 0 and r["verified"] == evens_in(a, b)
                                for r, (a, b) in zip(res, ivs)),
-           "results_consistent": res2 == res, "params": gb.get_params()}
+           "results_consistent": res2 == res, "params": params,
+           "launch_device_ms_each": dev, "launch_device_ms_median": dev_ms,
+           "roofline": batch_roofline(params, ev, dev_ms)}
     if not per_interval:
         return out
     log("batched: %d intervals in %.3f s per launch (median of %d); per-interval baseline next"
