@@ -144,7 +144,8 @@ __device__ inline bool w_slucas(u128w q, uint32_t qi, u128w one_u)
     // 0 < |Q| <= 2^14 + 1 (|D| < 2^16 + 5 by the bound on the search): the
     // Montgomery forms of Q and of V_2 = P^2 - 2Q come from a small-constant
     // product and a negation
-    u128w Qm_u = w_mul_small(one_u, (uint32_t)(Qs < 0 ? -Qs : Qs), q, w_recip_d(q));
+    const double qr = w_recip_d(q);
+    u128w Qm_u = w_mul_small(one_u, (uint32_t)(Qs < 0 ? -Qs : Qs), q, qr);
     if (Qs < 0 && !w_zero(Qm_u))
         Qm_u = w_sub(q, Qm_u);
     const u128w V2_u = w_submod(one_u, w_addmod(Qm_u, Qm_u, q), q);
@@ -161,11 +162,13 @@ __device__ inline bool w_slucas(u128w q, uint32_t qi, u128w one_u)
     //   V_2k = V_k^2 - 2 Q^k,  V_2k+1 = V_k V_k+1 - P Q^k,  V_2k+2 = V_k+1^2 - 2 Q^k+1.
     // U is not carried: D U_k = 2 V_k+1 - P V_k, and D is a unit mod q
     // ((D / q) = -1), so U_d = 0 (mod q) exactly when 2 V_d+1 = P V_d.  Every
-    // step is the same four Montgomery products whatever the bit (no
-    // divergence); the subtractions are additions of 2q - Q^k and
-    // 2 (2q - Q^(k+bit)), so V_k and V_k+1 stay below 5.02 q unreduced.
+    // step is the same three Montgomery products and one product by the small
+    // integer Q (Q^k+1 = Q Q^k, at most 3q) whatever the bit (no divergence);
+    // the subtractions are additions of 2q - Q^k and 2 (3q - Q^(k+bit)), so
+    // V_k and V_k+1 stay below 7.02 q unreduced.
     const wl<N> q5 = wl_from<N>(q.lo, q.hi);
     const wl<N> twoq = wl_norm(wl_add(q5, q5));
+    const wl<N> threeq = wl_norm(wl_add(twoq, q5));
     const wl<N> Qm = wl_from<N>(Qm_u.lo, Qm_u.hi);
     const int top = d.hi ? 127 - __builtin_clzll(d.hi) : 63 - __builtin_clzll(d.lo);
     wl<N> V = wl_from<N>(one_u.lo, one_u.hi);   // V_1 = P = 1
@@ -174,18 +177,18 @@ __device__ inline bool w_slucas(u128w q, uint32_t qi, u128w one_u)
     for (int i = top - 1; i >= 0; --i) {
         const uint64_t w = i >= 64 ? d.hi : d.lo;
         const bool bit = ((w >> (i & 63)) & 1) != 0;
-        const wl<N> QkQ = wl_mont(Qk, Qm, q5, qi);
-        const wl<N> Qb = bit ? QkQ : Qk;        // Q^(k + bit), below 1.02 q
+        const wl<N> QkQ = wl_mul_q(Qk, Qs, q5, qr);
+        const wl<N> Qb = bit ? QkQ : Qk;        // Q^(k + bit), at most 3q
         const wl<N> x = bit ? V1 : V;
         const wl<N> prod = wl_add(wl_mont(V, V1, q5, qi), wl_sub(twoq, Qk));
-        const wl<N> nb = wl_sub(twoq, Qb);
+        const wl<N> nb = wl_sub(threeq, Qb);
         const wl<N> sq = wl_add(wl_mont(x, x, q5, qi), wl_add(nb, nb));
         V = bit ? prod : sq;
         V1 = bit ? sq : prod;
         Qk = wl_mont(Qk, Qb, q5, qi);           // Q^(2k + bit)
     }
-    V = wl_canon<N, 5>(V, q5);
-    V1 = wl_canon<N, 5>(V1, q5);
+    V = wl_canon<N, 7>(V, q5);
+    V1 = wl_canon<N, 7>(V1, q5);
     if (wl_eq(wl_canon<N, 1>(wl_add(V1, V1), q5), V) || wl_zero(V))
         return true;   // U_d = 0 or V_d = 0
     for (int r = 1; r < s; ++r) {

@@ -101,6 +101,36 @@ GB_WIDE_FN wl<N> wl_mont(const wl<N> &a, const wl<N> &b, const wl<N> &q, uint32_
     return r;
 }
 
+// Q x mod q for a small signed integer Q (0 < |Q| < 2^15) and x normalized with
+// a value below 1.02 q (a Montgomery product's output), in the Montgomery form
+// of x's residue times Q; qrecip = 1/q in double precision.  The result is
+// normalized with a value in [0, 3q].  The quotient t of |Q| x by q is below
+// 2^16 and its double-precision estimate e has a relative error below 2^-49,
+// so e is t - 1, t or t + 1; then |Q| x - (e - 1) q (e >= 1; |Q| x when e = 0,
+// where t <= 1) lies in [0, 3q) and (e + 2) q - |Q| x in (0, 3q].  One pass of
+// signed multiply-adds forms Q x + u q limb by limb, u = 1 - e or e + 2.
+template <int N>
+GB_WIDE_FN wl<N> wl_mul_q(const wl<N> &x, int32_t Q, const wl<N> &q, double qrecip)
+{
+    double xd = (double)x.l[N - 1];
+#pragma unroll
+    for (int j = N - 2; j >= 0; --j)
+        xd = xd * 268435456.0 + (double)x.l[j];
+    const uint32_t a = Q < 0 ? (uint32_t)(-Q) : (uint32_t)Q;
+    const int32_t e = (int32_t)((double)a * xd * qrecip);
+    const int32_t u = Q < 0 ? e + 2 : (e > 0 ? 1 - e : 0);
+    wl<N> r;
+    int64_t c = 0;
+#pragma unroll
+    for (int j = 0; j < N - 1; ++j) {
+        c += (int64_t)(int32_t)x.l[j] * Q + (int64_t)(int32_t)q.l[j] * u;
+        r.l[j] = (uint32_t)c & kLimbMask;
+        c >>= 28;   // arithmetic: the floor of c / 2^28
+    }
+    r.l[N - 1] = (uint32_t)(c + (int64_t)(int32_t)x.l[N - 1] * Q + (int64_t)(int32_t)q.l[N - 1] * u);
+    return r;
+}
+
 // x + y limb by limb (no carries: the caller keeps the operand bounds).
 template <int N>
 GB_WIDE_FN wl<N> wl_add(const wl<N> &x, const wl<N> &y)

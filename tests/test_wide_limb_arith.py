@@ -5,7 +5,8 @@ seeded moduli of the sizes each N serves and operands at the limits of the
 documented bounds (limbs up to 2^30 - 1, values up to 8q - 1) the product is
 congruent to a b / R mod q, its limbs below the top one are normalized and its
 value is below a b / R + q, and the reduction and subtraction helpers give the
-exact residues -- and the 128-bit helpers (gb_wide_u128.h).  Exact integers
+exact residues, and the product by a small signed Q gives Q x mod q at most
+3q -- and the 128-bit helpers (gb_wide_u128.h).  Exact integers
 decide."""
 import os
 import shutil
@@ -29,10 +30,11 @@ def test_limb_montgomery_product_and_helpers():
                         os.path.join(HERE, "wide_limb_arith.cpp")], check=True)
         out = subprocess.run([exe, "40000", "7"], capture_output=True, text=True, timeout=600,
                              check=True).stdout.splitlines()
-    assert len(out) == 80000
+    assert len(out) == 120000
     lazy = 0
     sizes = set()
-    for mline, hline in zip(out[0::2], out[1::2]):
+    qs = set()
+    for mline, hline, qline in zip(out[0::3], out[1::3], out[2::3]):
         f = mline.split()
         assert f[0] == "mont"
         N, qi = int(f[1]), int(f[2], 16)
@@ -53,7 +55,17 @@ def test_limb_montgomery_product_and_helpers():
         assert val(yl) == r % q and max(yl[:N - 1]) < (1 << 28)   # canonical
         assert val(zl) == 2 * q - r and max(zl[:N - 1]) < (1 << 28)
         assert val(sl) == (r + 3 * (2 * q - r)) % q
+        g = qline.split()
+        assert g[0] == "mulq"
+        Q = int(g[1])
+        ml = [int(x, 16) for x in g[2:2 + N]]
+        m = val(ml)
+        assert 0 < abs(Q) <= (1 << 14) + 1
+        assert (m - Q * r) % q == 0 and 0 <= m <= 3 * q   # Q r mod q, at most 3q
+        assert max(ml[:N - 1]) < (1 << 28)
+        qs.add(Q)
     assert sizes == {3, 4, 5}
+    assert {1, -1, (1 << 14) + 1, -(1 << 14) - 1} <= qs
     assert lazy > 10000   # the lazy operand forms were exercised
 
 

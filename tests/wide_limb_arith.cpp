@@ -106,6 +106,19 @@ static void one_case()
     put(z);
     put(s);
     printf("\n");
+    // the product by a small signed Q (0 < |Q| <= 2^14 + 1) of the Montgomery
+    // product's output (below 1.02 q), the edges of Q's range drawn often
+    const int32_t edges[6] = {1, 2, 3, (1 << 14) - 1, 1 << 14, (1 << 14) + 1};
+    const uint32_t pick = (uint32_t)(next64() % 8);
+    int32_t Q = pick < 6 ? edges[pick] : 1 + (int32_t)(next64() % ((1 << 14) + 1));
+    if (next64() & 1)
+        Q = -Q;
+    const double qrecip = 1.0 / ((double)(uint64_t)(q >> 64) * 18446744073709551616.0 +
+                                 (double)(uint64_t)q);
+    const wl<N> m = wl_mul_q(r, Q, q5, qrecip);
+    printf("mulq %d", Q);
+    put(m);
+    printf("\n");
 }
 
 int main(int argc, char **argv)
