@@ -22,7 +22,7 @@ def gb():
     return g
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_boundary_calls():
     names = _declared()
     for n in ("gb_base_primes", "gb_verify_range", "gb_verify_batch", "gb_last_error",
               "gb_is_prime_u64", "gb_autotune", "gb_release"):
