@@ -15,7 +15,7 @@ Extra legs (also in the JSON line):
                 kernel) over the kernel time from HIP events on the launch
                 stream, against the gfx950 VALU peak; beside it the VALU issue
                 fraction from the counters;
-  c1            every even n in [4, 10^10] (base primes <= 10^5);
+  range_1e10    every even n in [4, 10^10] (base primes <= 10^5);
   batched       4096 seeded uneven intervals reaching 2^64 - 2 in one
                 persistent launch (median of 5 launches, with the 2^32 table
                 build end to end) vs one launch per interval; its roofline is
@@ -428,7 +428,7 @@ def run_served(gb, capacity_evens_per_s, load=0.7, n_requests=2000, seed=3001):
     return out
 
 
-def run_c1(gb, steps, prices=None):
+def run_range_1e10(gb, steps, prices=None):
     """Every even n in [4, 10^10] with base primes <= 10^5: one step = table
     build + verification, launch parameters from the autotuner on the whole
     range.  Its roofline takes the work model's units for this range and
@@ -451,7 +451,7 @@ def run_c1(gb, steps, prices=None):
     ev = evens_in(A, B)
     dt = statistics.median(each)
     kmed = statistics.median(kern)
-    ops_even = algorithmic_ops_per_even(work_model(), prices, params["seg_log2"], "c1")
+    ops_even = algorithmic_ops_per_even(work_model(), prices, params["seg_log2"], "range_1e10")
     achieved = ops_even * ev / (kmed / 1e3) if ops_even else None
     roof = {"bound": "alu", "achieved": achieved / 1e12 if achieved else None,
             "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
@@ -663,7 +663,7 @@ def main():
         "roofline": roofline,
         "timing": timing,
     }
-    out["c1"] = run_c1(gb, args.steps, prices)
+    out["range_1e10"] = run_range_1e10(gb, args.steps, prices)
     if not args.no_batched:
         # batches reach 2^64: their launch parameters come from the batch
         # autotuner on every 8th interval of the batch (unless --params)

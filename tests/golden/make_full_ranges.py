@@ -12,8 +12,8 @@ thread pool (the oracle's C calls release the GIL) and merged with the
 associative rules of the aggregates (sums mod 2^64, max with the smallest-n
 tie, lists concatenated in ascending order).
 
-Run:  python tests/golden/make_full_ranges.py [c1] [c2] [c3] [--threads N]
-(about 25 min for c2 and 40 min for c3 on 8 cores).
+Run:  python tests/golden/make_full_ranges.py [1e10] [1e12] [batch] [--threads N]
+(about 25 min for 1e12 and 40 min for batch on 8 cores).
 """
 import concurrent.futures as cf
 import json
@@ -102,24 +102,24 @@ def main():
     if "--threads" in sys.argv:
         threads = int(sys.argv[sys.argv.index("--threads") + 1])
         args = [a for a in args if a != str(threads)]
-    todo = args or ["c1", "c2", "c3"]
-    if "c1" in todo:
+    todo = args or ["1e10", "1e12", "batch"]
+    if "1e10" in todo:
         t = time.time()
         total, _ = full_range(10**10, 10**5, 10**10, 10**8, threads)
         write_json("full_1e10.json", {
             "what": "oracle aggregates of every even n in [4, 10^10]; prime table to 10^5; "
                     "P_max = 2^16; written by make_full_ranges.py",
             "limit": 10**5, "result": total})
-        log("c1 %.0f s" % (time.time() - t))
-    if "c2" in todo:
+        log("[4, 1e10] %.0f s" % (time.time() - t))
+    if "1e12" in todo:
         t = time.time()
         total, sl = full_range(10**12, 10**6, 10**10 // 2, 10**9 // 2, threads)
         write_json("full_1e12.json", {
             "what": "oracle aggregates of every even n in [4, 10^12]; prime table to 10^6; "
                     "P_max = 2^16; slices of 5e9 evens; written by make_full_ranges.py",
             "limit": 10**6, "result": total, "slices": sl})
-        log("c2 %.0f s" % (time.time() - t))
-    if "c3" in todo:
+        log("[4, 1e12] %.0f s" % (time.time() - t))
+    if "batch" in todo:
         t = time.time()
         T = 2**32 - 1
         O.primes(T)
@@ -150,7 +150,7 @@ def main():
         path = os.path.join(HERE, "batch_4096.txt")
         with open(path, "w") as f:
             f.write("\n".join(lines) + "\n")
-        log("wrote %s; c3 %.0f s" % (path, time.time() - t))
+        log("wrote %s; batch %.0f s" % (path, time.time() - t))
 
 
 if __name__ == "__main__":

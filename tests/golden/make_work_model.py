@@ -20,7 +20,7 @@ The p_min come from the oracle; the strike counts are exact counts of
 multiples in each sampled window.  Sampled segments are spread uniformly over
 the range (the range is uniform in n).
 
-With --c1 it adds (or replaces) the "c1" section only: the same units for
+With --range-1e10 it adds (or replaces) the "range_1e10" section only: the same units for
 every even n in [4, 10^10] with base primes <= 10^5 and probe window 16384,
 per segment size.
 
@@ -30,7 +30,7 @@ method must make, one per table prime p with bound < p <= isqrt(top) per
 interval (an interval's prime must be located once; all its later multiples
 follow by adding p), per even, for bitmap bounds 2^21 .. 2^25.
 
-Run:  python tests/golden/make_work_model.py [--c1 | --batch]
+Run:  python tests/golden/make_work_model.py [--range-1e10 | --batch]
 """
 import json
 import math
@@ -140,18 +140,18 @@ def batch_section():
 
 
 def main():
-    if "--c1" in sys.argv:
+    if "--range-1e10" in sys.argv:
         path = os.path.join(HERE, "work_model.json")
         with open(path) as f:
             out = json.load(f)
         rng = np.random.default_rng(1010)
-        out["c1"] = {"range": [4, 10**10], "base_prime_limit": 10**5,
+        out["range_1e10"] = {"range": [4, 10**10], "base_prime_limit": 10**5,
                      "configs": {str(lg): model(lg, rng, (4, 10**10), 10**5, 16384)
                                  for lg in (18, 19, 20)}}
         with open(path, "w") as f:
             json.dump(out, f, indent=1)
             f.write("\n")
-        print(json.dumps(out["c1"], indent=1))
+        print(json.dumps(out["range_1e10"], indent=1))
         return
     if "--batch" in sys.argv:
         path = os.path.join(HERE, "work_model.json")

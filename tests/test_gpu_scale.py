@@ -106,7 +106,7 @@ SHAPES_C1 = [dict(seg_log2=18, wg_size=256, window=4096, bucket_log2=0),
              dict(seg_log2=20, wg_size=1024, window=4096, bucket_log2=0)]
 
 
-def test_c1_full_range_and_windows(gb, O):
+def test_range_1e10_full_and_windows(gb, O):
     """Every even n in [4, 10^10], base primes up to 10^5, P_max = 2^16, at the
     three segment sizes: the whole range against the oracle's aggregates of it
     (tests/golden/full_1e10.json), the first 10^9 and the 64 seeded 10^7-wide
@@ -118,7 +118,7 @@ def test_c1_full_range_and_windows(gb, O):
     full = None
     for shape in SHAPES_C1:
         gb.set_params(**shape)
-        log("c1 shape %s" % shape)
+        log("[4,1e10] shape %s" % shape)
         same(gb.verify_range(4, 10**9, 65536), o1, what="[4,1e9] %s" % shape)
         for (a, b), o, g in zip(wins, ow, gb.verify_batch(wins, 65536)):
             same(g, o, what="window %d %s" % (a, shape))
@@ -138,7 +138,7 @@ def test_c1_full_range_and_windows(gb, O):
             same(f, full, FIELDS, "[4,1e10] shape %s" % shape)
 
 
-def test_c2_headline_range(gb, O):
+def test_range_1e12_headline(gb, O):
     """Every even n in [4, 10^12], base primes up to 10^6, P_max = 2^16, in the
     benchmark's launch configurations: the whole range and its 100 slices of
     5e9 evens against the oracle's aggregates (tests/golden/full_1e12.json),
@@ -155,24 +155,24 @@ def test_c2_headline_range(gb, O):
     full = None
     for cfg in configs:
         gb.set_params(**cfg)
-        log("c2 params %s" % cfg)
+        log("[4,1e12] params %s" % cfg)
         same(gb.verify_range(4, 10**9, 65536), o1, what="[4,1e9] %s" % cfg)
         for (a, b), o, g in zip(wins, ow, gb.verify_batch(wins, 65536)):
             same(g, o, what="window %d %s" % (a, cfg))
         t = time.time()
         f = gb.verify_range(4, 10**12, 65536)
-        log("c2 full range %.3f s: %s" % (time.time() - t, {k: f[k] for k in AGG}))
+        log("[4,1e12] full range %.3f s: %s" % (time.time() - t, {k: f[k] for k in AGG}))
         same(f, g12["result"], FIELDS, "[4,1e12] against the oracle's full-range aggregates %s"
              % cfg)
         assert f["max_p"] >= max(o["max_p"] for o in ow + [o1])
         if full is None:
             full = f
             rng = random.Random(7)
-            c1 = 2 * rng.randrange(10**9, 2 * 10**11)
-            c2 = 2 * rng.randrange(2 * 10**11, 5 * 10**11)
-            parts = [gb.verify_range(4, c1, 65536), gb.verify_range(c1 + 2, c2, 65536),
-                     gb.verify_range(c2 + 2, 10**12, 65536)]
-            same(merge_gpu(O, parts), f, AGG, "split of [4,1e12] at %d, %d" % (c1, c2))
+            cut1 = 2 * rng.randrange(10**9, 2 * 10**11)
+            cut2 = 2 * rng.randrange(2 * 10**11, 5 * 10**11)
+            parts = [gb.verify_range(4, cut1, 65536), gb.verify_range(cut1 + 2, cut2, 65536),
+                     gb.verify_range(cut2 + 2, 10**12, 65536)]
+            same(merge_gpu(O, parts), f, AGG, "split of [4,1e12] at %d, %d" % (cut1, cut2))
             # the oracle's 100 slices of 5e9 evens, in one batched launch
             sl = g12["slices"]
             for o, g in zip(sl, gb.verify_batch([(x["A"], x["B"]) for x in sl], 65536)):
@@ -196,7 +196,7 @@ def golden_batch():
     return rows
 
 
-def test_c3_batch(gb, O):
+def test_batch_4096_intervals(gb, O):
     """The seeded batch of 4096 uneven intervals (16 ending next to 2^64 - 2),
     base primes up to 2^32, in one batched launch with the automatic
     strike-bitmap policy: every interval bit-exact against the oracle's result
@@ -211,7 +211,7 @@ def test_c3_batch(gb, O):
     assert len(want) == len(ivs) == 4096
     t = time.time()
     got = gb.verify_batch(ivs, 65536)
-    log("c3 batch %.3f s" % (time.time() - t))
+    log("batch of 4096 intervals %.3f s" % (time.time() - t))
     for (a, b), g, o in zip(ivs, got, want):
         assert (o["A"], o["B"]) == (a, b) == (g["A"], g["B"])
         for f in AGG:
@@ -225,7 +225,7 @@ def test_c3_batch(gb, O):
     assert got2 == got
     short = [i for i, (a, b) in enumerate(ivs) if evens(a, b) <= 1 << 20]
     pick = random.Random(11).sample(short, 16)
-    log("c3 live oracle sample: %d intervals" % len(pick))
+    log("batch live oracle sample: %d intervals" % len(pick))
     O.primes(T)   # build the oracle's table once, before the threads share it
     ow = oracle_many(O, [(ivs[i][0], ivs[i][1], 65536, T, 1 << 22) for i in pick])
     for i, o in zip(pick, ow):
