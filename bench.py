@@ -236,8 +236,8 @@ def host_info():
 
 def cpu_baseline(sample_windows):
     """The oracle, as it stands: aggregate over seeded windows of the headline
-    range on the host's cores (at most 16: the CPU share of one GPU on the
-    box), and single-thread rates on [4, 10^8], a 10^7-wide window near 10^12,
+    range on the host's cores (at most 16: the CPU share of one GPU on a
+    shared host), and single-thread rates on [4, 10^8], a 10^7-wide window near 10^12,
     2^24 evens ending at 2^64 - 2 and 2^12 evens from 2^64 (the wide oracle,
     Baillie-PSW)."""
     from concurrent.futures import ThreadPoolExecutor
@@ -543,7 +543,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build measures one MI355X; --gpus %d is not supported "
+        print("bench.py: measures one MI355X; --gpus %d is not supported "
               "(the verification shards by segments, see the design notes)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)

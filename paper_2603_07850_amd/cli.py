@@ -227,11 +227,11 @@ def parse_args(argv):
     ap.add_argument("--resume", action="store_true", help="continue the run recorded in --log")
     ap.add_argument("--unresolved-cap", type=int, default=1 << 16,
                     help="unresolved evens kept in the output")
-    ap.add_argument("--gpus", type=int, default=1, help="GPUs to use (this build drives one)")
+    ap.add_argument("--gpus", type=int, default=1, help="GPUs to use (the verifier drives one)")
     ap.add_argument("--max-chunks", type=int, default=None, help=argparse.SUPPRESS)
     a = ap.parse_args(argv)
     if a.gpus != 1:
-        ap.error("--gpus=%d: this build verifies on one GPU; partition the range across jobs "
+        ap.error("--gpus=%d: the verifier runs on one GPU; partition the range across jobs "
                  "with --start instead" % a.gpus)
     if a.resume and not a.log:
         ap.error("--resume needs --log")
