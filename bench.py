@@ -544,7 +544,7 @@ def main():
 
     if args.gpus != 1:
         print("bench.py: measures one MI355X; --gpus %d is not supported "
-              "(the verification shards by segments, see the design notes)" % args.gpus,
+              "(several GPUs would each verify a contiguous share of the range, one process per GPU)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
